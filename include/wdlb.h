@@ -1,0 +1,172 @@
+/*
+ * wdlb.h -- C ABI of the MI355X (gfx950) weighted-density lattice Boltzmann
+ * (WDLB) library, libwdlb.so.
+ *
+ * The method is the isothermal SMDB/WDA lattice Boltzmann scheme for a
+ * hard-sphere fluid of Marini Bettolo Marconi & Melchionna (arXiv:1304.7880):
+ * a D3Q19 lattice whose collision carries the mean-field and viscous forces
+ * of the hard-sphere contact shell and the SMDB relaxation field A_ij
+ * (Sec. 3), evaluated with the Carnahan-Starling contact value at the
+ * Fischer-Methfessel weighted density (Sec. 3), and advanced by the
+ * five-step algorithm of Sec. 5 (initialise; fields; collide and stream;
+ * new moments; repeat).  Geometry: a slit pore between two smooth parallel
+ * walls normal to z (half-way bounce-back), periodic in x and y; or a fully
+ * periodic box.
+ *
+ * Conventions for every call:
+ *   - Every function returns a wdlb_status; no C++ exception crosses the ABI.
+ *   - Host pointers (h_*) are borrowed for the duration of the call only.
+ *   - Device memory is owned by the caller: the library carves its arrays out
+ *     of one caller-allocated device workspace that must outlive the context.
+ *     The library never frees caller memory and allocates no device memory.
+ *   - All GPU work is enqueued on the caller's HIP stream (desc.stream;
+ *     NULL = the default stream).  Calls that return host data synchronise
+ *     that stream.
+ *   - One host thread per context; contexts are independent.
+ *   - Node order is x fastest: i = (z*ny + y)*nx + x, z = 0 the first fluid
+ *     plane next to the lower wall.  Vector fields are component-major
+ *     (u[c*N + i]).  Populations use the D3Q19 order
+ *       0:(0,0,0) 1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1)
+ *       6:(0,0,-1) 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1)
+ *       12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1)
+ *       17:(0,1,-1) 18:(0,-1,1).
+ *   - Lattice units: spacing, time step and particle mass are 1; kT = 1/3.
+ */
+#ifndef WDLB_H
+#define WDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WDLB_OK = 0,
+    WDLB_E_INVAL = 1,          /* bad argument: shape, sigma < 1, tau <= 1/2, eta outside (0,1), size */
+    WDLB_E_NOMEM = 2,          /* workspace smaller than wdlb_workspace_size reports */
+    WDLB_E_HIP = 3,            /* a HIP call failed; wdlb_last_error has its message */
+    WDLB_E_UNSTABLE = 4,       /* non-finite or non-positive density, or a midpoint packing fraction >= 1 */
+    WDLB_E_STATE = 5,          /* call out of order (e.g. step before init) or state buffer mismatch */
+    WDLB_E_NOT_CONVERGED = 6   /* a serving request hit its step cap */
+} wdlb_status;
+
+typedef enum {
+    WDLB_FP64 = 0,             /* FP64 storage and arithmetic */
+    WDLB_FP32 = 1,             /* FP32 storage and arithmetic, FP64 reductions */
+    WDLB_BF16_NEQ = 2          /* BF16 storage of f - f_eq, FP32 arithmetic */
+} wdlb_precision;
+
+typedef struct wdlb_ctx wdlb_ctx;  /* opaque */
+
+/* Lattice: fluid nodes nx * ny * nz.  walls_z = 1: walls at z = -1/2 and
+ * nz - 1/2 (the slit width H = nz); walls_z = 0: periodic in z. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t walls_z;
+    int32_t precision;         /* wdlb_precision */
+    void *stream;              /* hipStream_t, or NULL */
+} wdlb_lattice_desc;
+
+/* Physical parameters (Sec. 5: sigma a multiple of the lattice spacing;
+ * eta = pi sigma^3 n / 6 the packing fraction of the uniform initial state;
+ * omega_0 = 1/tau; g the external force per unit mass of eq. (1)).
+ * nonlocal = 0 drops the hard-sphere fields (plain forced BGK); smdb = 0
+ * drops the A_ij relaxation term (the DSB form of Sec. 2). */
+typedef struct {
+    double sigma;
+    double eta;
+    double tau;
+    double g[3];
+    int32_t nonlocal;
+    int32_t smdb;
+} wdlb_params;
+
+/* Bytes of device workspace a context with this lattice needs (independent
+ * of sigma up to sigma = 24).  *bytes receives the size. */
+wdlb_status wdlb_workspace_size(const wdlb_lattice_desc *desc, const wdlb_params *params, size_t *bytes);
+
+/* Create a context on the current HIP device.  d_workspace: device memory of
+ * at least wdlb_workspace_size bytes, 256-byte aligned, owned by the caller.
+ * On success *out receives the context; nothing is initialised until one of
+ * the wdlb_init_* calls. */
+wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params, void *d_workspace,
+                        size_t bytes, wdlb_ctx **out);
+
+/* Replace sigma, tau, g, nonlocal, smdb (eta only matters for init). */
+wdlb_status wdlb_set_params(wdlb_ctx *ctx, const wdlb_params *params);
+
+/* Sec. 5, step 1: f = f_eq(n0, u0) at every node, n0 = 6 eta/(pi sigma^3). */
+wdlb_status wdlb_init_uniform(wdlb_ctx *ctx, const double u0[3]);
+
+/* Sec. 5, step 1 from given fields: h_n[N] density, h_u[3N] velocity (FP64,
+ * host).  f = f_eq(n, u) at every node. */
+wdlb_status wdlb_init_fields(wdlb_ctx *ctx, const double *h_n, const double *h_u);
+
+/* Sec. 5, steps 2-5 repeated nsteps times: fields, collide + stream with
+ * bounce-back, new moments.  Asynchronous on the stream; instability is
+ * flagged on the device and reported by the next synchronising call. */
+wdlb_status wdlb_step(wdlb_ctx *ctx, int64_t nsteps);
+
+/* Block until the stream has drained; WDLB_E_UNSTABLE if any step so far
+ * met a non-finite or non-positive density or a packing fraction >= 1. */
+wdlb_status wdlb_sync(wdlb_ctx *ctx);
+
+/* Fields at the current time (Sec. 5, step 4): density h_n[N] and velocity
+ * h_u[3N] = (j + F/2)/rho, FP64 host arrays.  Either pointer may be NULL.
+ * Synchronises. */
+wdlb_status wdlb_read_fields(wdlb_ctx *ctx, double *h_n, double *h_u);
+
+/* As wdlb_read_fields plus the total force density h_F[3N] =
+ * rho (g + F^mf + F^v) and the traceless symmetric SMDB field h_A0[9N]
+ * (row-major 3x3 per node).  Any pointer may be NULL. */
+wdlb_status wdlb_read_fields_ex(wdlb_ctx *ctx, double *h_n, double *h_u, double *h_F, double *h_A0);
+
+/* Plane means at the current time, reduced on the device in FP64:
+ * h_n_z[nz] = <rho>_xy and h_ux_z[nz] = <u_x>_xy.  Either may be NULL. */
+wdlb_status wdlb_read_profiles(wdlb_ctx *ctx, double *h_n_z, double *h_ux_z);
+
+/* Pore-averaged properties at the current time (FP64 device reductions):
+ * j_pore = sum(rho u_x)/N (mass flux), u_pore = mean over z of <u_x>_xy,
+ * mass = sum(rho).  Any pointer may be NULL. */
+wdlb_status wdlb_read_flux(wdlb_ctx *ctx, double *j_pore, double *u_pore, double *mass);
+
+/* Current post-stream populations f_a (19N, FP64, order above). */
+wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);
+
+/* Checkpoint: the complete state (populations in their stored encoding and
+ * the step count) in wdlb_state_size bytes, copied to / from a host buffer.
+ * A state can only be loaded into a context with the same lattice and
+ * precision (WDLB_E_STATE otherwise). */
+wdlb_status wdlb_state_size(const wdlb_ctx *ctx, size_t *bytes);
+wdlb_status wdlb_save_state(wdlb_ctx *ctx, void *h_buf, size_t bytes);
+wdlb_status wdlb_load_state(wdlb_ctx *ctx, const void *h_buf, size_t bytes);
+
+/* Steps taken since the last init or load. */
+wdlb_status wdlb_get_step(const wdlb_ctx *ctx, int64_t *step);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every kernel launch of wdlb_step (off by default; a few microseconds of
+ * event overhead per launch when on).  wdlb_profile(ctx, 1) enables and
+ * resets the totals, wdlb_profile(ctx, 0) disables.  wdlb_profile_read
+ * synchronises and returns, for kernel id k (0 .. WDLB_NKERNELS-1), the
+ * summed device time in milliseconds and the number of launches timed.
+ * wdlb_kernel_name(k) names the kernel ("" for an unknown id). */
+#define WDLB_NKERNELS 5
+wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t enable);
+wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+const char *wdlb_kernel_name(int32_t kernel);
+
+/* Message of the last failed call on this context ("" if none).  The
+ * pointer stays valid until the next call on the context. */
+const char *wdlb_last_error(const wdlb_ctx *ctx);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void wdlb_destroy(wdlb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDLB_H */

@@ -1,0 +1,91 @@
+// d3q19.hpp -- lattice constants and per-node arithmetic of the WDLB step
+// on gfx950.  Device code only; included by wdlb.hip.
+//
+// Storage encoding of the populations.  After the collision at node s the
+// library keeps the node's density and velocity (rho_s, u_s) and the
+// deviation h_a(s) = f*_a(s) - feq_a(rho_s, u_s).  A population streamed to
+// node r is then
+//     f_a(r) = w_a rho_s  +  [ w_a rho_s P_a(u_s) + h_a(s) ],
+//     P_a(u) = 3 c_a.u + 9/2 (c_a.u)^2 - 3/2 u.u,
+// and the two parts are never added into one number: the momentum of the
+// rest part is formed from density differences of mirror-image sources and
+// the collision works on f - feq in difference form.  Every quantity that
+// carries the flow (j, f - feq) is therefore computed from small numbers and
+// keeps full relative precision in FP32, where plain FP32 populations lose
+// about four digits of the momentum to cancellation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wdlb {
+
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// the populations with c = +1 along an axis, and their mirror images across it
+constexpr int PX[5] = {1, 7, 9, 11, 13}, MXP[5] = {2, 10, 8, 14, 12};
+constexpr int PY[5] = {3, 7, 10, 15, 17}, MYP[5] = {4, 9, 8, 18, 16};
+constexpr int PZ[5] = {5, 11, 14, 15, 18}, MZP[5] = {6, 13, 12, 17, 16};
+
+template <typename R>
+__host__ __device__ constexpr R wgt(int a)
+{
+    return a == 0 ? R(1) / R(3) : (a <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+
+template <typename R>
+struct alignas(4 * sizeof(R)) V4 {
+    R x, y, z, w;
+};
+
+// h storage type: R itself for FP32/FP64; 16-bit brain float for BF16.
+struct bf16 {
+    uint16_t bits;
+};
+
+template <typename R>
+__device__ __forceinline__ R load_h(const R *p) { return *p; }
+template <typename R>
+__device__ __forceinline__ void store_h(R *p, R v) { *p = v; }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    // round to nearest even; NaN stays NaN
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+// P_a(u) for the velocity a (compile-time after unrolling)
+template <typename R>
+__device__ __forceinline__ R pterm(int a, R ux, R uy, R uz)
+{
+    R cu = R(CX[a]) * ux + R(CY[a]) * uy + R(CZ[a]) * uz;
+    R uu = ux * ux + uy * uy + uz * uz;
+    return R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+}
+
+struct Geom {
+    int nx, ny, nz, walls;
+    long long N;
+    int tiny;  // 1 when an axis is shorter than the stencil reach: wrap by modulo
+};
+
+__device__ __forceinline__ int wrap1(int v, int n)
+{
+    // v in [-n, 2n)
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
+__device__ __forceinline__ int wrapm(int v, int n)
+{
+    int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
+}  // namespace wdlb

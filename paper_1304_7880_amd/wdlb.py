@@ -1,0 +1,236 @@
+"""Python binding of libwdlb.so (the C ABI in include/wdlb.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of the library.  PyTorch provides the device workspace and the
+stream.  There is no fallback: if the library or a GPU is missing the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwdlb.so")
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_NOT_CONVERGED = range(7)
+STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSTABLE", 5: "E_STATE", 6: "E_NOT_CONVERGED"}
+FP64, FP32, BF16_NEQ = 0, 1, 2
+NKERNELS = 5
+PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ}
+
+# D3Q19 order of the library's populations (include/wdlb.h)
+CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+               [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
+               [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
+
+SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
+           "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
+           "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
+           "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_last_error",
+           "wdlb_destroy"]
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls_z", C.c_int32),
+                ("precision", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("eta", C.c_double), ("tau", C.c_double), ("g", C.c_double * 3),
+                ("nonlocal_", C.c_int32), ("smdb", C.c_int32)]
+
+
+class WdlbError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libwdlb.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "or python -m paper_1304_7880_amd.build")
+    import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+    L = C.CDLL(path)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    L.wdlb_workspace_size.argtypes = [C.POINTER(LatticeDesc), C.POINTER(Params), C.POINTER(C.c_size_t)]
+    L.wdlb_create.argtypes = [C.POINTER(LatticeDesc), C.POINTER(Params), vp, C.c_size_t, C.POINTER(vp)]
+    L.wdlb_set_params.argtypes = [vp, C.POINTER(Params)]
+    L.wdlb_init_uniform.argtypes = [vp, dp]
+    L.wdlb_init_fields.argtypes = [vp, dp, dp]
+    L.wdlb_step.argtypes = [vp, C.c_int64]
+    L.wdlb_sync.argtypes = [vp]
+    L.wdlb_read_fields.argtypes = [vp, dp, dp]
+    L.wdlb_read_fields_ex.argtypes = [vp, dp, dp, dp, dp]
+    L.wdlb_read_profiles.argtypes = [vp, dp, dp]
+    L.wdlb_read_flux.argtypes = [vp, dp, dp, dp]
+    L.wdlb_read_populations.argtypes = [vp, dp]
+    L.wdlb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.wdlb_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.wdlb_load_state.argtypes = [vp, vp, C.c_size_t]
+    L.wdlb_get_step.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.wdlb_profile.argtypes = [vp, C.c_int32]
+    L.wdlb_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
+    L.wdlb_kernel_name.argtypes = [C.c_int32]
+    L.wdlb_kernel_name.restype = C.c_char_p
+    L.wdlb_last_error.argtypes = [vp]
+    L.wdlb_last_error.restype = C.c_char_p
+    L.wdlb_destroy.argtypes = [vp]
+    L.wdlb_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_desc(nx, ny, nz, walls_z=True, precision="fp32", stream=None) -> LatticeDesc:
+    return LatticeDesc(int(nx), int(ny), int(nz), int(bool(walls_z)), PRECISION[precision]
+                       if isinstance(precision, str) else int(precision), stream)
+
+
+def make_params(sigma=4.0, eta=0.2, tau=1.0, g=(0.0, 0.0, 0.0), nonlocal_=True, smdb=True) -> Params:
+    return Params(float(sigma), float(eta), float(tau), (C.c_double * 3)(*[float(v) for v in g]),
+                  int(bool(nonlocal_)), int(bool(smdb)))
+
+
+def workspace_size(desc: LatticeDesc, params: Params) -> int:
+    n = C.c_size_t(0)
+    st = load().wdlb_workspace_size(C.byref(desc), C.byref(params), C.byref(n))
+    if st != OK:
+        raise WdlbError(st, "workspace_size")
+    return n.value
+
+
+class Context:
+    """One lattice on the current device; the workspace is a torch uint8 tensor."""
+
+    def __init__(self, nx, ny, nz, walls_z=True, precision="fp32", sigma=4.0, eta=0.2, tau=1.0,
+                 g=(0.0, 0.0, 0.0), nonlocal_=True, smdb=True, stream=None, device="cuda"):
+        import torch
+        L = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.desc = make_desc(nx, ny, nz, walls_z, precision, C.c_void_p(stream.cuda_stream))
+        self.params = make_params(sigma, eta, tau, g, nonlocal_, smdb)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.N = self.nx * self.ny * self.nz
+        nbytes = workspace_size(self.desc, self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        st = L.wdlb_create(C.byref(self.desc), C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
+                           nbytes, C.byref(h))
+        if st != OK:
+            raise WdlbError(st, "wdlb_create")
+        self.h = h
+        self._L = L
+
+    # -- plumbing -----------------------------------------------------------
+    def _chk(self, st, what):
+        if st != OK:
+            msg = self._L.wdlb_last_error(self.h)
+            raise WdlbError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self._L.wdlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    # -- the C entry points ---------------------------------------------------
+    def set_params(self, sigma, eta, tau, g, nonlocal_=True, smdb=True):
+        self.params = make_params(sigma, eta, tau, g, nonlocal_, smdb)
+        self._chk(self._L.wdlb_set_params(self.h, C.byref(self.params)), "set_params")
+
+    def init_uniform(self, u0=(0.0, 0.0, 0.0)):
+        u = np.ascontiguousarray(u0, dtype=np.float64)
+        self._chk(self._L.wdlb_init_uniform(self.h, _ptr(u)), "init_uniform")
+
+    def init_fields(self, n, u):
+        n = np.ascontiguousarray(n, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        if n.size != self.N or u.size != 3 * self.N:
+            raise ValueError("field sizes do not match the lattice")
+        self._chk(self._L.wdlb_init_fields(self.h, _ptr(n), _ptr(u)), "init_fields")
+
+    def step(self, nsteps=1):
+        self._chk(self._L.wdlb_step(self.h, int(nsteps)), "step")
+
+    def sync(self):
+        self._chk(self._L.wdlb_sync(self.h), "sync")
+
+    def read_fields(self, with_forces=False):
+        N = self.N
+        n, u = np.zeros(N), np.zeros(3 * N)
+        if not with_forces:
+            self._chk(self._L.wdlb_read_fields(self.h, _ptr(n), _ptr(u)), "read_fields")
+            return n, u
+        F, A0 = np.zeros(3 * N), np.zeros(9 * N)
+        self._chk(self._L.wdlb_read_fields_ex(self.h, _ptr(n), _ptr(u), _ptr(F), _ptr(A0)), "read_fields_ex")
+        return n, u, F, A0
+
+    def read_profiles(self):
+        nz_, ux = np.zeros(self.nz), np.zeros(self.nz)
+        self._chk(self._L.wdlb_read_profiles(self.h, _ptr(nz_), _ptr(ux)), "read_profiles")
+        return nz_, ux
+
+    def read_flux(self):
+        j, u, m = C.c_double(), C.c_double(), C.c_double()
+        self._chk(self._L.wdlb_read_flux(self.h, C.byref(j), C.byref(u), C.byref(m)), "read_flux")
+        return j.value, u.value, m.value
+
+    def read_populations(self):
+        f = np.zeros(19 * self.N)
+        self._chk(self._L.wdlb_read_populations(self.h, _ptr(f)), "read_populations")
+        return f
+
+    def state_size(self):
+        n = C.c_size_t()
+        self._chk(self._L.wdlb_state_size(self.h, C.byref(n)), "state_size")
+        return n.value
+
+    def save_state(self) -> bytes:
+        n = self.state_size()
+        buf = C.create_string_buffer(n)
+        self._chk(self._L.wdlb_save_state(self.h, buf, n), "save_state")
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._chk(self._L.wdlb_load_state(self.h, buf, len(data)), "load_state")
+
+    def profile(self, enable=True):
+        self._chk(self._L.wdlb_profile(self.h, int(bool(enable))), "profile")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} of the timed step kernels (synchronises)."""
+        out = {}
+        for k in range(NKERNELS):
+            ms, n = C.c_double(), C.c_int64()
+            self._chk(self._L.wdlb_profile_read(self.h, k, C.byref(ms), C.byref(n)), "profile_read")
+            out[self._L.wdlb_kernel_name(k).decode()] = (ms.value, n.value)
+        return out
+
+    def get_step(self):
+        s = C.c_int64()
+        self._chk(self._L.wdlb_get_step(self.h, C.byref(s)), "get_step")
+        return s.value

@@ -1,0 +1,211 @@
+"""GPU (HIP, gfx950) against the FP64 oracle, element by element.
+
+Every case runs the library through its C ABI and the oracle on the same
+seeded inputs.  FP64 on the GPU must agree to round-off.  FP32 must agree
+within 1e-5 relative on the flow (u_x(z) and the pore-averaged flux) of the
+slit workloads.  On random fields the shell sums cancel: with 5 % density
+noise the mean-field force is about 300 times smaller than the sum of the
+magnitudes of its |S| terms, so FP32 round-off there is ~300 x 6e-8 of the
+largest force; the random-field FP32 tolerances (1e-4 on rho, u, f; 1e-3 on
+F and A0, relative to the largest value) are that round-off, not a looser
+physics target.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1304_7880_amd.workloads import (SLAB_64, SLAB_SMALL, initial_fields, packing_to_density,
+                                           random_fields)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(nx, ny, nz, walls, prec, sigma, eta, tau, g, nonlocal_=True, smdb=True):
+    from paper_1304_7880_amd import wdlb
+    return wdlb.Context(nx, ny, nz, walls, prec, sigma, eta, tau, g, nonlocal_, smdb)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    # (name, shape, walls, sigma, eta, tau, g, steps)
+    ("walled 21x19x13 sigma=3 (several tiles, ragged)", (21, 19, 13), True, 3.0, 0.3, 0.8, (1e-4, 2e-5, 0.0), 4),
+    ("periodic 9x7x11 sigma=4 (stencil wraps)", (9, 7, 11), False, 4.0, 0.25, 1.1, (0.0, 3e-5, 1e-5), 3),
+    ("walled 4x4x16 sigma=4 (domain smaller than stencil)", (4, 4, 16), True, 4.0, 0.2, 1.0, (1e-4, 0, 0), 5),
+    ("walled 17x5x23 sigma=6", (17, 5, 23), True, 6.0, 0.35, 0.8, (2e-5, 0, 0), 3),
+]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_random_fields_few_steps(case, prec, tol):
+    name, (nx, ny, nz), walls, sigma, eta, tau, g, steps = case
+    _say(f"case {name} {prec}")
+    n0 = packing_to_density(eta, sigma)
+    n, u = random_fields(nx, ny, nz, n0, 0.05, 0.01, seed=7)
+    cfg = ref.Config(nx, ny, nz, walls, sigma, tau, g)
+    st = ref.State.from_fields(cfg, n, u)
+    ctx = _ctx(nx, ny, nz, walls, prec, sigma, eta, tau, g)
+    ctx.init_fields(n, u)
+    for k in range(steps + 1):
+        rho_o, u_o, F_o, A_o = st.fields()
+        rho_g, u_g, F_g, A_g = ctx.read_fields(with_forces=True)
+        assert _rel(rho_g, rho_o) < tol, ("rho", k)
+        assert _rel(u_g, u_o) < tol, ("u", k)
+        assert _rel(F_g, F_o) < 10 * tol, ("F", k)
+        assert _rel(A_g, A_o) < 10 * tol, ("A0", k)
+        f_g = ctx.read_populations()
+        assert _rel(f_g, st.f) < tol, ("f", k)
+        if k < steps:
+            st.step(1)
+            ctx.step(1)
+    ctx.sync()
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_small_slab_full_run(prec, tol):
+    """The 4x4x16 slit (sigma = 4, eta = 0.2, tau = 1, g_x = 1e-6), 2000 steps:
+    n(z), u_x(z) and the pore-averaged flux against the oracle."""
+    w = SLAB_SMALL
+    _say(f"slab {w.name} {prec}")
+    n, u = initial_fields(w)
+    cfg = ref.Config(w.nx, w.ny, w.nz, w.walls_z, w.sigma, w.tau, w.g)
+    st = ref.State.from_fields(cfg, n, u)
+    st.step(w.steps)
+    nz_o, ux_o, J_o, up_o, M_o = st.reduce()
+    ctx = _ctx(w.nx, w.ny, w.nz, True, prec, w.sigma, w.eta, w.tau, w.g)
+    ctx.init_fields(n, u)
+    ctx.step(w.steps)
+    ctx.sync()
+    nz_g, ux_g = ctx.read_profiles()
+    J_g, up_g, M_g = ctx.read_flux()
+    _say(f"  u_x(z) rel err {_rel(ux_g, ux_o):.3e}  J rel err {abs(J_g - J_o) / abs(J_o):.3e}")
+    assert _rel(ux_g, ux_o) < tol
+    assert abs(J_g - J_o) < tol * abs(J_o)
+    assert abs(up_g - up_o) < tol * abs(up_o)
+    assert _rel(nz_g, nz_o) < tol
+    assert abs(M_g - M_o) < 1e-6 * M_o
+    ctx.destroy()
+
+
+def test_plain_bgk_poiseuille_closed_form():
+    """nonlocal = 0: forced BGK between walls reaches the exact profile
+    g/(2 nu) (z_w^2 - z^2) + g (4 l^2 - 3)/(4 l)."""
+    H, g, tau = 16, 1e-5, 1.3
+    ctx = _ctx(8, 8, H, True, "fp32", 4.0, 0.2, tau, (g, 0, 0), nonlocal_=False)
+    ctx.init_fields(np.ones(8 * 8 * H), np.zeros(3 * 8 * 8 * H))
+    nu = (tau - 0.5) / 3
+    ctx.step(int(40 * H * H / (nu * math.pi ** 2)))
+    _, ux = ctx.read_profiles()
+    z = np.arange(H) - (H - 1) / 2
+    lam = 2 * tau - 1
+    pred = g / (2 * nu) * ((H / 2) ** 2 - z ** 2) + g * (4 * lam ** 2 - 3) / (4 * lam)
+    _say(f"  poiseuille rel err {_rel(ux, pred):.3e}")
+    # FP32 storage of u limits a steady state to about eps_32 times the
+    # slowest relaxation time in steps (H^2/(pi^2 nu) = 73 here): ~5e-6
+    assert _rel(ux, pred) < 2e-5
+    ctx.destroy()
+
+
+def test_mass_conservation_and_uniform_fixed_point():
+    nx, ny, nz = 12, 10, 9
+    ctx = _ctx(nx, ny, nz, False, "fp64", 3.0, 0.3, 0.9, (0, 0, 0))
+    ctx.init_uniform((1e-3, -2e-3, 5e-4))
+    f0 = ctx.read_populations()
+    ctx.step(5)
+    f1 = ctx.read_populations()
+    assert _rel(f1, f0) < 1e-14
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, 3.0), 0.05, 0.01, seed=1)
+    ctx2 = _ctx(nx, ny, nz, True, "fp32", 3.0, 0.3, 0.9, (1e-4, 0, 0))
+    ctx2.init_fields(n, u)
+    M0 = ctx2.read_flux()[2]
+    ctx2.step(50)
+    M1 = ctx2.read_flux()[2]
+    assert abs(M1 - M0) < 1e-5 * M0
+    ctx.destroy()
+    ctx2.destroy()
+
+
+def test_checkpoint_resume_and_determinism():
+    nx, ny, nz = 16, 12, 10
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, 4.0), 0.05, 0.01, seed=5)
+    a = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (1e-5, 0, 0))
+    a.init_fields(n, u)
+    a.step(7)
+    snap = a.save_state()
+    a.step(9)
+    fa = a.read_populations()
+    b = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (1e-5, 0, 0))
+    b.load_state(snap)
+    assert b.get_step() == 7
+    b.step(9)
+    fb = b.read_populations()
+    assert np.array_equal(fa, fb)
+    c = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (1e-5, 0, 0))
+    c.init_fields(n, u)
+    c.step(16)
+    assert np.array_equal(c.read_populations(), fa)
+    for x in (a, b, c):
+        x.destroy()
+
+
+def test_instability_is_reported():
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz = 8, 8, 8
+    ctx = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (0, 0, 0))
+    n = np.full(nx * ny * nz, packing_to_density(0.3, 4.0))
+    n[100] = np.nan
+    ctx.init_fields(n, np.zeros(3 * n.size))
+    ctx.step(2)
+    with pytest.raises(wdlb.WdlbError) as e:
+        ctx.sync()
+    assert e.value.status == wdlb.E_UNSTABLE
+    # a packing fraction above 1 at the midpoints
+    ctx2 = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (0, 0, 0))
+    ctx2.init_fields(np.full(n.size, packing_to_density(1.2, 4.0)), np.zeros(3 * n.size))
+    ctx2.step(1)
+    with pytest.raises(wdlb.WdlbError) as e:
+        ctx2.sync()
+    assert e.value.status == wdlb.E_UNSTABLE
+    ctx.destroy()
+    ctx2.destroy()
+
+
+def test_slab64_full_size_first_steps():
+    """The 64^3 slit (sigma = 6, eta = 0.35, tau = 0.8, +-1 % noise) at full
+    size in FP32 against the oracle for the first steps."""
+    w = SLAB_64
+    steps = 3
+    _say(f"slab64 {steps} steps")
+    n, u = initial_fields(w)
+    cfg = ref.Config(w.nx, w.ny, w.nz, True, w.sigma, w.tau, w.g)
+    st = ref.State.from_fields(cfg, n, u)
+    st.step(steps)
+    rho_o, u_o, F_o, A_o = st.fields()
+    nz_o, ux_o, J_o, _, _ = ref.reduce_fields(cfg, rho_o, u_o)
+    ctx = _ctx(w.nx, w.ny, w.nz, True, "fp32", w.sigma, w.eta, w.tau, w.g)
+    ctx.init_fields(n, u)
+    ctx.step(steps)
+    rho_g, u_g, F_g, A_g = ctx.read_fields(with_forces=True)
+    _say(f"  rho {_rel(rho_g, rho_o):.2e} u {_rel(u_g, u_o):.2e} F {_rel(F_g, F_o):.2e} A {_rel(A_g, A_o):.2e}")
+    assert _rel(rho_g, rho_o) < 1e-5
+    assert _rel(u_g, u_o) < 1e-5
+    assert _rel(F_g, F_o) < 1e-4
+    assert _rel(A_g, A_o) < 1e-4
+    nz_g, ux_g = ctx.read_profiles()
+    # after 3 steps the plane means are ~1e-3 of the node velocities (the
+    # noise-driven flow averages out), so compare them on the node scale
+    assert np.abs(ux_g - ux_o).max() < 1e-5 * np.abs(u_o).max()
+    assert _rel(nz_g, nz_o) < 1e-6
+    ctx.destroy()
