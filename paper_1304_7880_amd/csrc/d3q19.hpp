@@ -2,17 +2,18 @@
 // on gfx950.  Device code only; included by wdlb.hip.
 //
 // Storage encoding of the populations.  After the collision at node s the
-// library keeps the node's density and velocity (rho_s, u_s) and the
-// deviation h_a(s) = f*_a(s) - feq_a(rho_s, u_s).  A population streamed to
-// node r is then
-//     f_a(r) = w_a rho_s  +  [ w_a rho_s P_a(u_s) + h_a(s) ],
+// library keeps the node's density and post-collision velocity
+// u*_s = (j + F)/rho and the deviation h_a(s) = f*_a(s) - feq_a(rho_s, u*_s),
+// which carries no mass and no momentum.  A population streamed to node r is
+//     f_a(r) = w_a rho_s  +  w_a rho_s P_a(u*_s)  +  h_a(s),
 //     P_a(u) = 3 c_a.u + 9/2 (c_a.u)^2 - 3/2 u.u,
-// and the two parts are never added into one number: the momentum of the
-// rest part is formed from density differences of mirror-image sources and
-// the collision works on f - feq in difference form.  Every quantity that
-// carries the flow (j, f - feq) is therefore computed from small numbers and
-// keeps full relative precision in FP32, where plain FP32 populations lose
-// about four digits of the momentum to cancellation.
+// and the three parts are never added into one number before the moments
+// are formed from differences of mirror-image sources.  The flow therefore
+// lives in u* (full FP32 relative precision) instead of in differences of
+// populations of size w rho: plain FP32 populations lose about four digits
+// of the momentum, and an encoding against the collision velocity u leaves
+// half the force in h, where the large wall-normal mean-field force of the
+// layers next to a wall swamps the small driving force in FP32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -72,68 +72,61 @@ __device__ __forceinline__ void raise_flag(int *flag, int bit)
 }
 
 // ---------------------------------------------------------------------------
-// pull: the 19 populations arriving at (x, y, z), kept as three parts
-//   f_a = w_a rs[a] + eq[a] + hh[a]
-// rs = source density, eq = w rs P(u_s) (the equilibrium's flow part),
-// hh = the stored deviation.  Near a wall hh carries the large mean-field
-// force terms while eq carries the momentum; adding them before the mirror
-// differences of the moments would lose the momentum to FP32 rounding.
+// pull: the population arriving at (x, y, z) with velocity c_a,
+//   f_a = w_a rho_s (1 + P_a(u*_s)) + h_a(s),
+// from the source s = r - c_a, or by half-way bounce-back from r itself.
+// The pull, the moments and the collision run in FP64 arithmetic: near a
+// wall u* has a large wall-normal part (half the mean-field force per unit
+// mass) next to a tiny flow part, and FP32 products c.u* and sums of
+// populations of size w rho lose the flow to rounding.  FP64 sums of the
+// stored parts are exact enough that no special summation order is needed.
+// On gfx950 an FP64 FMA issues at the rate of an unpacked FP32 FMA, and this
+// part is a few percent of the step's arithmetic; storage keeps the
+// precision of the mode.
 // ---------------------------------------------------------------------------
+typedef double D;
+
 template <typename R, typename HS>
-__device__ __forceinline__ void pull(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
-                                     int x, int y, int z, R rs[Q], R eq[Q], R hh[Q])
+__device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, int x,
+                                   int y, int z, int r, int a)
 {
-    const long long N = g.N;
-    const int r = (z * g.ny + y) * g.nx + x;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        int sz = z - CZ[a];
-        bool bb = false;
-        if (CZ[a] != 0) {
-            if (g.walls) bb = (sz < 0 || sz >= g.nz);
-            else sz = wrap1(sz, g.nz);
-        }
-        int s;
-        long long hi;
-        if (bb) {
-            s = r;
-            hi = (long long)OPP[a] * N + r;
-        } else {
-            int sx = CX[a] ? wrap1(x - CX[a], g.nx) : x;
-            int sy = CY[a] ? wrap1(y - CY[a], g.ny) : y;
-            s = (sz * g.ny + sy) * g.nx + sx;
-            hi = (long long)a * N + s;
-        }
-        V4<R> q = ru[s];
-        R cu = R(CX[a]) * q.y + R(CY[a]) * q.z + R(CZ[a]) * q.w;
-        if (bb) cu = -cu;
-        R uu = q.y * q.y + q.z * q.z + q.w * q.w;
-        R P = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
-        rs[a] = q.x;
-        eq[a] = wgt<R>(a) * q.x * P;
-        hh[a] = ldh<R, HS>(h + hi);
+    int sz = z - CZ[a];
+    bool bb = false;
+    if (CZ[a] != 0) {
+        if (g.walls) bb = (sz < 0 || sz >= g.nz);
+        else sz = wrap1(sz, g.nz);
     }
+    int s, ha;
+    if (bb) {
+        s = r;
+        ha = OPP[a];
+    } else {
+        int sx = CX[a] ? wrap1(x - CX[a], g.nx) : x;
+        int sy = CY[a] ? wrap1(y - CY[a], g.ny) : y;
+        s = (sz * g.ny + sy) * g.nx + sx;
+        ha = a;
+    }
+    const V4<R> q = ru[s];
+    const D ux = q.y, uy = q.z, uz = q.w;
+    D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
+    if (bb) cu = -cu;
+    const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * (ux * ux + uy * uy + uz * uz);
+    return wgt<D>(a) * D(q.x) * (D(1) + P) + D(ldh<R, HS>(h + (long long)ha * g.N + s));
 }
 
-// density and momentum; each momentum component is a sum over mirror pairs
-// (c_i = +1 and its image) of the differences of the three parts
-template <typename R>
-__device__ __forceinline__ void moments(const R rs[Q], const R eq[Q], const R hh[Q], R &rho, R &jx, R &jy, R &jz)
+template <typename R, typename HS>
+__device__ __forceinline__ void pull_moments(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
+                                             int x, int y, int z, D &rho, D &jx, D &jy, D &jz)
 {
-    R big = 0, e = 0, d = 0;
+    const int r = (z * g.ny + y) * g.nx + x;
+    rho = jx = jy = jz = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        big += wgt<R>(a) * rs[a];
-        e += eq[a];
-        d += hh[a];
-    }
-    rho = big + (e + d);
-    jx = jy = jz = 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        jx += wgt<R>(PX[k]) * (rs[PX[k]] - rs[MXP[k]]) + (eq[PX[k]] - eq[MXP[k]]) + (hh[PX[k]] - hh[MXP[k]]);
-        jy += wgt<R>(PY[k]) * (rs[PY[k]] - rs[MYP[k]]) + (eq[PY[k]] - eq[MYP[k]]) + (hh[PY[k]] - hh[MYP[k]]);
-        jz += wgt<R>(PZ[k]) * (rs[PZ[k]] - rs[MZP[k]]) + (eq[PZ[k]] - eq[MZP[k]]) + (hh[PZ[k]] - hh[MZP[k]]);
+        const D f = fpull<R, HS>(g, ru, h, x, y, z, r, a);
+        rho += f;
+        if (CX[a]) jx += D(CX[a]) * f;
+        if (CY[a]) jy += D(CY[a]) * f;
+        if (CZ[a]) jz += D(CZ[a]) * f;
     }
 }
 
@@ -152,7 +145,7 @@ __device__ __forceinline__ bool node_of(const Geom &g, long long i, int &x, int 
 // kernels
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_fill(Geom g, V4<R> *ru, R n0, R ux, R uy, R uz)
+__global__ __launch_bounds__(256) void k_fill(Geom g, V4<R> *ru, R n0, R ux, R uy, R uz)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < g.N) ru[i] = V4<R>{n0, ux, uy, uz};
@@ -164,7 +157,7 @@ __global__ void k_fill(Geom g, V4<R> *ru, R n0, R ux, R uy, R uz)
 // when t lies in a wall, the value that bounces back into s itself,
 // feq_abar(n(s), u(s)); h is that minus feq_a(n(s), u(s)) in difference form.
 template <typename R, typename HS>
-__global__ void k_init(Geom g, const V4<R> *__restrict__ ru, HS *__restrict__ h)
+__global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ ru, HS *__restrict__ h)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
@@ -198,24 +191,23 @@ __global__ void k_init(Geom g, const V4<R> *__restrict__ ru, HS *__restrict__ h)
 }
 
 template <typename R, typename HS>
-__global__ void k_moments(Geom g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, R *__restrict__ rho,
+__global__ __launch_bounds__(256) void k_moments(Geom g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, R *__restrict__ rho,
                           R *__restrict__ jx, R *__restrict__ jy, R *__restrict__ jz, int *flag)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
-    R rs[Q], eq[Q], hh[Q], r, a, b, c;
-    pull<R, HS>(g, ru, h, x, y, z, rs, eq, hh);
-    moments<R>(rs, eq, hh, r, a, b, c);
-    if (!(r > R(0)) || !(r < R(INFINITY))) raise_flag(flag, FLAG_RHO);
-    rho[i] = r;
-    jx[i] = a;
-    jy[i] = b;
-    jz[i] = c;
+    D r, a, b, c;
+    pull_moments<R, HS>(g, ru, h, x, y, z, r, a, b, c);
+    if (!(r > D(0)) || !(r < D(INFINITY))) raise_flag(flag, FLAG_RHO);
+    rho[i] = R(r);
+    jx[i] = R(a);
+    jy[i] = R(b);
+    jz[i] = R(c);
 }
 
 template <typename R>
-__global__ void k_ball(Geom g, const R *__restrict__ rho, const int4 *__restrict__ ball, int nball, R inv_nball,
+__global__ __launch_bounds__(256) void k_ball(Geom g, const R *__restrict__ rho, const int4 *__restrict__ ball, int nball, R inv_nball,
                        R *__restrict__ nbar)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,7 +230,7 @@ __global__ void k_ball(Geom g, const R *__restrict__ rho, const int4 *__restrict
 }
 
 template <typename R>
-__global__ void k_gamma(Geom g, const R *__restrict__ nbar, R eta_per_n, R wS, R *__restrict__ gam, int *flag)
+__global__ __launch_bounds__(256) void k_gamma(Geom g, const R *__restrict__ nbar, R eta_per_n, R wS, R *__restrict__ gam, int *flag)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
@@ -305,7 +297,7 @@ __device__ __forceinline__ Member member(const Geom &g, int x, int y, int z, int
 }
 
 template <typename R>
-__global__ void k_meanfield(Geom g, const R *__restrict__ rho, const R *__restrict__ jx, const R *__restrict__ jy,
+__global__ __launch_bounds__(256) void k_meanfield(Geom g, const R *__restrict__ rho, const R *__restrict__ jx, const R *__restrict__ jy,
                             const R *__restrict__ jz, const R *__restrict__ gam,
                             const Quad<R> *__restrict__ quads, int nq, R cmf, R gx, R gy, R gz,
                             V4<R> *__restrict__ ru1, V4<R> *__restrict__ fmf)
@@ -338,7 +330,7 @@ __global__ void k_meanfield(Geom g, const R *__restrict__ rho, const R *__restri
 }
 
 template <typename R, typename HS, bool READ>
-__global__ void k_collide(Geom g, const V4<R> *__restrict__ ru1, const V4<R> *__restrict__ fmf,
+__global__ __launch_bounds__(256) void k_collide(Geom g, const V4<R> *__restrict__ ru1, const V4<R> *__restrict__ fmf,
                           const R *__restrict__ gam, const Quad<R> *__restrict__ quads, int nq, R cv, R cA,
                           R omega, R ksrc, R gx, R gy, R gz, int smdb, const V4<R> *__restrict__ ru_in,
                           const HS *__restrict__ h_in, V4<R> *__restrict__ ru_out, HS *__restrict__ h_out,
@@ -394,16 +386,16 @@ __global__ void k_collide(Geom g, const V4<R> *__restrict__ ru1, const V4<R> *__
     Azz -= tr;
     if (!smdb) Axx = Ayy = Azz = Axy = Axz = Ayz = R(0);
 
-    R rs[Q], eq[Q], hh[Q], rho, jx, jy, jz;
-    pull<R, HS>(g, ru_in, h_in, x, y, z, rs, eq, hh);
-    moments<R>(rs, eq, hh, rho, jx, jy, jz);
-    R inv = R(1) / rho;
-    R ux = (jx + R(0.5) * Fx) * inv, uy = (jy + R(0.5) * Fy) * inv, uz = (jz + R(0.5) * Fz) * inv;
+    D rho, jx, jy, jz;
+    pull_moments<R, HS>(g, ru_in, h_in, x, y, z, rho, jx, jy, jz);
+    const D inv = D(1) / rho;
+    const D Fxd = Fx, Fyd = Fy, Fzd = Fz;
+    const D ux = (jx + D(0.5) * Fxd) * inv, uy = (jy + D(0.5) * Fyd) * inv, uz = (jz + D(0.5) * Fzd) * inv;
     if (READ) {
         const long long N = g.N;
-        u_rd[i] = ux;
-        u_rd[N + i] = uy;
-        u_rd[2 * N + i] = uz;
+        u_rd[i] = R(ux);
+        u_rd[N + i] = R(uy);
+        u_rd[2 * N + i] = R(uz);
         F_rd[i] = Fx;
         F_rd[N + i] = Fy;
         F_rd[2 * N + i] = Fz;
@@ -415,41 +407,51 @@ __global__ void k_collide(Geom g, const V4<R> *__restrict__ ru1, const V4<R> *__
         A_rd[5 * N + i] = Ayz;
         return;
     }
-    R uu = ux * ux + uy * uy + uz * uz;
-    R uF = ux * Fx + uy * Fy + uz * Fz;
-    R keep = R(1) - omega;
+    // Forced BGK with the SMDB source (trapezoidal weighting ksrc = 1 - 1/(2 tau)),
+    // stored against the post-collision velocity u* = u + F/(2 rho):
+    //   h*_a = (1 - omega)(f_a - feq_a(u)) + [feq_a(u) - feq_a(u*)] + ksrc (guo_a + sa_a)
+    // so the deviation carries no momentum and the flow lives in u* alone.
+    const D uu = ux * ux + uy * uy + uz * uz;
+    const D uF = ux * Fxd + uy * Fyd + uz * Fzd;
+    const D keep = D(1) - D(omega), ks = D(ksrc);
+    const D dx = D(0.5) * Fxd * inv, dy = D(0.5) * Fyd * inv, dz = D(0.5) * Fzd * inv;  // u* - u
+    const D sx = D(2) * ux + dx, sy = D(2) * uy + dy, sz = D(2) * uz + dz;                // u + u*
+    const D dsum = dx * sx + dy * sy + dz * sz;
+    const D Axxd = Axx, Ayyd = Ayy, Azzd = Azz, Axyd = Axy, Axzd = Axz, Ayzd = Ayz;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        const R w = wgt<R>(a);
-        R cu = R(CX[a]) * ux + R(CY[a]) * uy + R(CZ[a]) * uz;
-        R P = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
-        R fneq = w * (rs[a] - rho) + (eq[a] - w * rho * P) + hh[a];
-        R cF = R(CX[a]) * Fx + R(CY[a]) * Fy + R(CZ[a]) * Fz;
-        R guo = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        R cAc = R(CX[a] * CX[a]) * Axx + R(CY[a] * CY[a]) * Ayy + R(CZ[a] * CZ[a]) * Azz +
-                R(2 * CX[a] * CY[a]) * Axy + R(2 * CX[a] * CZ[a]) * Axz + R(2 * CY[a] * CZ[a]) * Ayz;
-        R sa = R(4.5) * w * cAc;
-        sth<R, HS>(h_out + (long long)a * g.N + i, keep * fneq + ksrc * (guo + sa));
+        const D w = wgt<D>(a);
+        const D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
+        const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * uu;
+        const D fneq = fpull<R, HS>(g, ru_in, h_in, x, y, z, (z * g.ny + y) * g.nx + x, a) - w * rho * (D(1) + P);
+        const D cF = D(CX[a]) * Fxd + D(CY[a]) * Fyd + D(CZ[a]) * Fzd;
+        const D guo = w * (D(3) * (cF - uF) + D(9) * cu * cF);
+        const D cAc = D(CX[a] * CX[a]) * Axxd + D(CY[a] * CY[a]) * Ayyd + D(CZ[a] * CZ[a]) * Azzd +
+                      D(2 * CX[a] * CY[a]) * Axyd + D(2 * CX[a] * CZ[a]) * Axzd + D(2 * CY[a] * CZ[a]) * Ayzd;
+        const D sa = D(4.5) * w * cAc;
+        const D cd = D(CX[a]) * dx + D(CY[a]) * dy + D(CZ[a]) * dz;
+        const D cs = D(CX[a]) * sx + D(CY[a]) * sy + D(CZ[a]) * sz;
+        const D deq = w * rho * (-D(3) * cd - D(4.5) * cd * cs + D(1.5) * dsum);
+        sth<R, HS>(h_out + (long long)a * g.N + i, R(keep * fneq + deq + ks * (guo + sa)));
     }
-    ru_out[i] = V4<R>{rho, ux, uy, uz};
+    ru_out[i] = V4<R>{R(rho), R(ux + dx), R(uy + dy), R(uz + dz)};
 }
 
 template <typename R, typename HS>
-__global__ void k_populations(Geom g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, R *__restrict__ f)
+__global__ __launch_bounds__(256) void k_populations(Geom g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, R *__restrict__ f)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
-    R rs[Q], eq[Q], hh[Q];
-    pull<R, HS>(g, ru, h, x, y, z, rs, eq, hh);
+    const int r = (z * g.ny + y) * g.nx + x;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) f[(long long)a * g.N + i] = wgt<R>(a) * rs[a] + (eq[a] + hh[a]);
+    for (int a = 0; a < Q; ++a) f[(long long)a * g.N + i] = R(fpull<R, HS>(g, ru, h, x, y, z, r, a));
 }
 
 // FP64 plane sums of rho, u_x and rho*u_x; one block per z-plane, fixed
 // reduction order (deterministic)
 template <typename R>
-__global__ void k_planes(Geom g, const R *__restrict__ rho, const R *__restrict__ ux, double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_planes(Geom g, const R *__restrict__ rho, const R *__restrict__ ux, double *__restrict__ out)
 {
     __shared__ double sh[3][256];
     const int z = blockIdx.x;
