@@ -44,6 +44,30 @@ def shell_flops_per_node(sigma: float) -> float:
     return 36.0 * shell_size(sigma)
 
 
+def shell_source_hash() -> str:
+    """sha256 (16 hex) of the k_shell kernel source, to tie counter data to it."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1304_7880_amd", "csrc", "kernels.hpp")).read()
+    a = src.index("template <typename R, int TX, int TY, int TZ, int NREG>")
+    b = src.index("\n}\n", a) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """Calibrated HBM bytes per k_shell launch from the rocprofv3 counter runs
+    summarised in profiles/, or None if k_shell changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "k_shell_slab64.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0].strip() in ("k_shell_traffic_bytes_per_launch", "k_shell_source_sha256_16"):
+            kv[line.split(":")[0].strip()] = line.split(":", 1)[1].strip()
+    if kv.get("k_shell_source_sha256_16") != shell_source_hash():
+        return None
+    return float(kv["k_shell_traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """The FP64 oracle on the same workload, stepped until budget_s elapsed."""
     from oracle import ref
@@ -69,6 +93,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
+                         "calibrating HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the WDLB step on a single MI355X "
@@ -85,6 +112,13 @@ def main():
         __graft_entry__.build()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, "fp32", w.sigma, w.eta, w.tau, w.g, stream=stream)
     n, u = initial_fields(w)
     ctx.init_fields(n, u)
@@ -131,7 +165,7 @@ def main():
                    "precision": "fp32 populations (f - feq encoding), fp64 reductions"},
         "roofline": {"bound": "alu", "kernel": "k_shell", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(),
                      "avg_kernel_ms": round(k_avg_s * 1e3, 5),
                      "flops_per_launch": flops},
         "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in kstats.items()},
