@@ -158,6 +158,27 @@ wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t enable);
 wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 const char *wdlb_kernel_name(int32_t kernel);
 
+/* Contact-shell kernel choice (a tuning and testing knob: every choice sums
+ * the same terms in the same order of mirror groups, so all of them give
+ * the same result).  The two shell kernels (mean-field force; viscous force
+ * and SMDB field) run on tiles of one of WDLB_NTILES variants:
+ *   0..2  32 x 8 x 2 nodes, contact values and (rho, u1) staged in LDS, for
+ *         growing shell reach;
+ *   3     32 x 16 x 1 nodes, both staged in LDS;
+ *   4     16 x 16 x 1 nodes, contact values read through the caches.
+ * wdlb_set_tile(ctx, -1) (the default) picks the first variant whose LDS
+ * rings fit the shell reach of sigma, and for sigma = 3, 4, 6, 8 or 10 runs
+ * kernels compiled for that shell (offsets and weights fixed at compile
+ * time) when that variant stages both fields in LDS.  A variant >= 0 forces
+ * that tile with the table-driven kernels and fails with WDLB_E_INVAL,
+ * leaving the previous choice, when it does not fit.  wdlb_set_params
+ * re-applies the request for the new sigma.  wdlb_get_tile returns the
+ * variant in use and (if specialised is not NULL) 1 when the compiled-shell
+ * kernels run, else 0. */
+#define WDLB_NTILES 5
+wdlb_status wdlb_set_tile(wdlb_ctx *ctx, int32_t variant);
+wdlb_status wdlb_get_tile(wdlb_ctx *ctx, int32_t *variant, int32_t *specialised);
+
 /* Message of the last failed call on this context ("" if none).  The
  * pointer stays valid until the next call on the context. */
 const char *wdlb_last_error(const wdlb_ctx *ctx);

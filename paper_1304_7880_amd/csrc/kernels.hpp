@@ -28,7 +28,10 @@
 // differences of mirror images before they are accumulated, so a state that
 // does not depend on x or y gives exactly zero x and y forces.
 #pragma once
+#include <utility>
+
 #include "d3q19.hpp"
+#include "shell.hpp"
 
 namespace wdlb {
 
@@ -252,9 +255,18 @@ __global__ __launch_bounds__(256) void k_ball(Geom g, Pad p, const R *__restrict
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const R *base = rho_p + pidx(p, x, y, z);
-    R s = 0;
-    for (int q = 0; q < nball; ++q) s += base[boff[q]];
-    const R v = s * inv_nball;
+    // four interleaved partial sums keep several gathers in flight; every
+    // node uses the same order, so x,y-uniform states stay exactly uniform
+    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int q = 0;
+    for (; q + 4 <= nball; q += 4) {
+        s0 += base[boff[q]];
+        s1 += base[boff[q + 1]];
+        s2 += base[boff[q + 2]];
+        s3 += base[boff[q + 3]];
+    }
+    for (; q < nball; ++q) s0 += base[boff[q]];
+    const R v = ((s0 + s1) + (s2 + s3)) * inv_nball;
     for_images(g, p, x, y, z, [&](int k) { nbar_p[k] = v; });
 }
 
@@ -310,207 +322,350 @@ __device__ __forceinline__ void quad_offsets(int a, int b, int c, int PX, int PX
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_meanfield(Geom g, Pad p, const R *__restrict__ rho_p,
-                                                   const R *__restrict__ jx, const R *__restrict__ jy,
-                                                   const R *__restrict__ jz, const R *__restrict__ gam_p,
-                                                   const Quad<R> *__restrict__ quads, int nq, R cmf, R gx, R gy,
-                                                   R gz, V4<R> *__restrict__ ru1_p, V4<R> *__restrict__ fmf)
+// ---------------------------------------------------------------------------
+// Contact-shell tiles (k_meanfield, k_shell).  A block owns a TX x TY x TZ
+// tile and runs over the shell as e_z = c from -R to R.  Two LDS rings
+// advance by one entry per c-step:
+//  - planes z0+c .. z0+c+TZ-1 of rho (k_meanfield) or of (rho, u1)
+//    (k_shell) over the tile plus an R-wide halo: TZ + 1 slots;
+//  - slices of the contact value.  Slice t = 2j + hz holds, for the padded
+//    z-plane z0 + j and z-parity hz, the four (x, y)-parity sub-lattices
+//    gamma_h over the tile plus the half-reach halo.  The half-lattice point
+//    r + e/2 of a node in tile plane lz lies in slice c + 2 lz, so step c
+//    reads slices c .. c + 2(TZ-1): 2 TZ slots with the one being fetched.
+// The next plane and slice are fetched into registers while the current c
+// is summed and stored after it; one barrier separates the c-steps.  With
+// NG = 0 gamma is read through L1/L2 from the padded arrays instead (tiles
+// whose rings do not fit in LDS).  Blocks are ordered so that each XCD gets
+// a contiguous run of tiles (shared halos stay in that XCD's L2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int id, int nb)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
-    const int b = pidx(p, x, y, z);
-    const R *rb = rho_p + b;
-    R fx = 0, fy = 0, fz = 0;
-    for (int q = 0; q < nq; ++q) {
-        const Quad<R> Qd = quads[q];
-        int so[4], mo[4];
-        quad_offsets(Qd.a, Qd.b, Qd.c, p.PX, p.PXY, so, mo);
-        const R *gb = gam_p + (long long)Qd.hidx * p.NP + b;
-        R hx, hy, h0;
-        {
-            // the mirror products and their Hadamard must not be fused into
-            // FMAs: fma(G0a, G0b, -G1) of identical mirror images is the
-            // rounding error of G1, not zero
-#pragma clang fp contract(off)
-            R G[4];
+    const int xcd = id & 7, qq = nb >> 3, rem = nb & 7;
+    return (xcd < rem ? xcd * (qq + 1) : rem * (qq + 1) + (xcd - rem) * qq) + (id >> 3);
+}
+
+struct TileCoord {
+    int x0, y0, z0, lx, ly, lz;
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int tiles_z)
+{
+    TileCoord t;
+    const int lid = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
+    const int t1 = lid / tiles_x;
+    t.x0 = (lid % tiles_x) * TX;
+    t.y0 = (t1 % tiles_y) * TY;
+    t.z0 = (t1 / tiles_y) * TZ;
+    t.lx = threadIdx.x % TX;
+    t.ly = (threadIdx.x / TX) % TY;
+    t.lz = threadIdx.x / (TX * TY);
+    return t;
+}
+
+// the gamma ring of one block: element e of a slice is sub-lattice
+// e / LG, row (e % LG) / LXg, column (e % LG) % LXg of the window whose
+// origin is the tile origin shifted by floor(-R/2) in x and y
+template <typename R, int NT, int NG>
+struct GammaRing {
+    int LXg, LG, LS;
+    int gh[NG], goff[NG];
+    R st[NG];
+
+    __device__ __forceinline__ void setup(const Pad &p, int Rr, int TX, int TY, int x0, int y0)
+    {
+        const int o = -((Rr + 1) >> 1);
+        LXg = TX + Rr;
+        LG = LXg * (TY + Rr);
+        LS = 4 * LG;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) G[m] = gb[mo[m]] * rb[so[m]];
-            const R P1 = G[0] + G[1], M1 = G[0] - G[1], P2 = G[2] + G[3], M2 = G[2] - G[3];
-            hx = M1 + M2;
-            hy = P1 - P2;
-            h0 = P1 + P2;
+        for (int k = 0; k < NG; ++k) {
+            const int e = min((int)threadIdx.x + k * NT, LS - 1);
+            gh[k] = e / LG;
+            const int rem = e - gh[k] * LG;
+            const int X = min(max(x0 + o + rem % LXg + p.P, 0), p.PX - 1);
+            const int Y = min(max(y0 + o + rem / LXg + p.P, 0), p.PY - 1);
+            goff[k] = Y * p.PX + X;
         }
-        fx += Qd.px * hx;
-        fy += Qd.py * hy;
-        fz += Qd.pz * h0;
     }
-    const R Fx = cmf * fx, Fy = cmf * fy, Fz = cmf * fz;
-    const R r = rb[0];
-    const R inv = R(1) / r;
-    const V4<R> v = {r, jx[i] * inv + R(0.5) * (gx + Fx), jy[i] * inv + R(0.5) * (gy + Fy),
+    // slice t (plane z0 + floor(t/2), z-parity t & 1) into registers
+    __device__ __forceinline__ void fetch(const R *__restrict__ gam_p, const Pad &p, int z0, int t)
+    {
+        const int hz = t & 1;
+        const long long zb = (long long)min(max(z0 + (t >> 1) + p.P, 0), p.PZ - 1) * p.PXY;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) st[k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
+    }
+    __device__ __forceinline__ void store(R *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int e = (int)threadIdx.x + k * NT;
+            if (e < LS) win[slot * LS + e] = st[k];
+        }
+    }
+};
+
+// ring of rho (V = R) or (rho, u1) (V = V4<R>) planes: element e of a plane
+// is row e / LX, column e % LX of the window whose origin is the tile origin
+// shifted by -R in x and y.  A staged float4 is kept as four scalars (an
+// array of vector structs would be placed in scratch memory).
+template <typename R>
+struct Comp {
+    static constexpr int n = 1;
+    __device__ static R get(const R &v, int) { return v; }
+    __device__ static void set(R &v, int, R x) { v = x; }
+};
+template <typename R>
+struct Comp<V4<R>> {
+    static constexpr int n = 4;
+    __device__ static R get(const V4<R> &v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)); }
+    __device__ static void set(V4<R> &v, int k, R x)
+    {
+        if (k == 0) v.x = x;
+        else if (k == 1) v.y = x;
+        else if (k == 2) v.z = x;
+        else v.w = x;
+    }
+};
+
+template <typename R, typename V, int NT, int NR>
+struct PlaneRing {
+    static constexpr int NC = Comp<V>::n;
+    int LX, LP;
+    int off[NR];
+    R st[NC][NR];
+
+    __device__ __forceinline__ void setup(const Pad &p, int Rr, int TX, int TY, int x0, int y0)
+    {
+        LX = TX + 2 * Rr;
+        LP = LX * (TY + 2 * Rr);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int e = min((int)threadIdx.x + k * NT, LP - 1);
+            const int X = min(max(x0 - Rr + e % LX + p.P, 0), p.PX - 1);
+            const int Y = min(max(y0 - Rr + e / LX + p.P, 0), p.PY - 1);
+            off[k] = Y * p.PX + X;
+        }
+    }
+    __device__ __forceinline__ void fetch(const V *__restrict__ src, const Pad &p, int pz)
+    {
+        const long long zb = (long long)min(max(pz + p.P, 0), p.PZ - 1) * p.PXY;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const V v = src[zb + off[k]];
+#pragma unroll
+            for (int m = 0; m < NC; ++m) st[m][k] = Comp<V>::get(v, m);
+        }
+    }
+    __device__ __forceinline__ void store(V *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int e = (int)threadIdx.x + k * NT;
+            if (e < LP) {
+                V v;
+#pragma unroll
+                for (int m = 0; m < NC; ++m) Comp<V>::set(v, m, st[m][k]);
+                win[slot * LP + e] = v;
+            }
+        }
+    }
+};
+
+// LDS bytes of the two rings (host and device agree on this layout: the
+// plane ring first, then the gamma ring)
+__host__ __device__ constexpr size_t shell_lds_bytes(int TX, int TY, int TZ, int Rr, size_t vbytes, size_t rbytes,
+                                                     bool gamma_lds)
+{
+    return (size_t)(TZ + 1) * (TX + 2 * Rr) * (TY + 2 * Rr) * vbytes +
+           (gamma_lds ? (size_t)(2 * TZ) * 4 * (TX + Rr) * (TY + Rr) * rbytes : 0);
+}
+
+// Both rings of one block and the per-lane pointers into them.  A c-step is
+//   begin(c)  fetch the next plane and slice into registers (c < R),
+//   ...       sum the quads of e_z = c from plane(c) and gamma(c),
+//   end(c)    store the fetched entries into the free slots, barrier.
+template <typename R, typename V, int TX, int TY, int TZ, int NR, int NG>
+struct ShellRings {
+    static constexpr int NT = TX * TY * TZ, NS = TZ + 1, NSG = 2 * TZ;
+    static constexpr bool GL = NG > 0;
+    PlaneRing<R, V, NT, NR> pr;
+    GammaRing<R, NT, GL ? NG : 1> gr;
+    V *win;
+    R *gwin;
+    int Rr, z0, lz, lbase, gcen;
+
+    __device__ __forceinline__ void init(unsigned char *lds, const Pad &p, int Rr_, const TileCoord &tc,
+                                         const V *__restrict__ src, const R *__restrict__ gam_p)
+    {
+        Rr = Rr_;
+        z0 = tc.z0;
+        lz = tc.lz;
+        pr.setup(p, Rr, TX, TY, tc.x0, tc.y0);
+        win = reinterpret_cast<V *>(lds);
+        gwin = reinterpret_cast<R *>(lds + (size_t)NS * pr.LP * sizeof(V));
+        lbase = (tc.ly + Rr) * pr.LX + (tc.lx + Rr);
+        const int o = (Rr + 1) >> 1;
+        gcen = 0;
+        if constexpr (GL) {
+            gr.setup(p, Rr, TX, TY, tc.x0, tc.y0);
+            gcen = (tc.ly + o) * gr.LXg + (tc.lx + o);
+        }
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            pr.fetch(src, p, z0 - Rr + k);
+            pr.store(win, k);
+        }
+        if constexpr (GL) {
+            for (int t = -Rr; t <= -Rr + 2 * TZ - 2; ++t) {
+                gr.fetch(gam_p, p, z0, t);
+                gr.store(gwin, (t + 64) % NSG);
+            }
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void begin(int c, const Pad &p, const V *__restrict__ src, const R *__restrict__ gam_p)
+    {
+        if (c < Rr) {
+            pr.fetch(src, p, z0 + c + TZ);
+            if constexpr (GL) gr.fetch(gam_p, p, z0, c + 2 * TZ - 1);
+        }
+    }
+    __device__ __forceinline__ void end(int c)
+    {
+        if (c < Rr) {
+            pr.store(win, (c + TZ + Rr) % NS);
+            if constexpr (GL) gr.store(gwin, (c + 2 * TZ - 1 + 64) % NSG);
+        }
+        __syncthreads();
+    }
+    // the lane's node in the plane window of e_z = c, and its half-lattice
+    // point in the gamma slice of e_z = c (both at in-plane offset 0)
+    __device__ __forceinline__ const V *plane(int c) const { return win + ((lz + c + Rr) % NS) * pr.LP + lbase; }
+    __device__ __forceinline__ const R *gamma(int c) const
+    {
+        return gwin + ((c + 2 * lz + 64) % NSG) * gr.LS + gcen;
+    }
+};
+
+// One quad of the mean-field sum: G_m = gamma_m rho_m for the four mirror
+// images and their Hadamard transform, accumulated with the quad's weights.
+// The mirror products and the transform must not be fused into FMAs:
+// fma(gamma_0, rho_0, -G_1) of identical mirror images is the rounding error
+// of G_1, not zero.
+template <typename R>
+__device__ __forceinline__ void mf_quad(const R (&gm)[4], const R (&rm)[4], R px, R py, R pz, R &fx, R &fy, R &fz)
+{
+    R hx, hy, h0;
+    {
+#pragma clang fp contract(off)
+        R G[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) G[m] = gm[m] * rm[m];
+        const R P1 = G[0] + G[1], M1 = G[0] - G[1], P2 = G[2] + G[3], M2 = G[2] - G[3];
+        hx = M1 + M2;
+        hy = P1 - P2;
+        h0 = P1 + P2;
+    }
+    fx += px * hx;
+    fy += py * hy;
+    fz += pz * h0;
+}
+
+// One quad of the viscous / SMDB sums: W_m = gamma_m rho_m (u1_m - u1_0),
+// the Hadamard transform over the mirror signs, accumulated with the quad's
+// weights (same no-fusion rule as mf_quad for the products and transform).
+template <typename R>
+__device__ __forceinline__ void sh_quad(const R (&gm)[4], const V4<R> (&sm)[4], const V4<R> &c0, R px, R py, R pz,
+                                        R qxx, R qyy, R qzz, R qxy, R qxz, R qyz, R (&acc)[9])
+{
+    R x0_, xX, xY, xXY, y0_, yX, yY, yXY, z0_, zX, zY;
+    {
+#pragma clang fp contract(off)
+        R Wx[4], Wy[4], Wz[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const R G = gm[m] * sm[m].x;
+            Wx[m] = G * (sm[m].y - c0.y);
+            Wy[m] = G * (sm[m].z - c0.z);
+            Wz[m] = G * (sm[m].w - c0.w);
+        }
+        const R xP1 = Wx[0] + Wx[1], xM1 = Wx[0] - Wx[1], xP2 = Wx[2] + Wx[3], xM2 = Wx[2] - Wx[3];
+        const R yP1 = Wy[0] + Wy[1], yM1 = Wy[0] - Wy[1], yP2 = Wy[2] + Wy[3], yM2 = Wy[2] - Wy[3];
+        const R zP1 = Wz[0] + Wz[1], zM1 = Wz[0] - Wz[1], zP2 = Wz[2] + Wz[3], zM2 = Wz[2] - Wz[3];
+        x0_ = xP1 + xP2;
+        xX = xM1 + xM2;
+        xY = xP1 - xP2;
+        xXY = xM1 - xM2;
+        y0_ = yP1 + yP2;
+        yX = yM1 + yM2;
+        yY = yP1 - yP2;
+        yXY = yM1 - yM2;
+        z0_ = zP1 + zP2;
+        zX = zM1 + zM2;
+        zY = zP1 - zP2;
+    }
+    // one FMA per term, in a fixed order
+    acc[0] += qxx * x0_;
+    acc[0] += qxy * yXY;
+    acc[0] += qxz * zX;
+    acc[1] += qxy * xXY;
+    acc[1] += qyy * y0_;
+    acc[1] += qyz * zY;
+    acc[2] += qxz * xX;
+    acc[2] += qyz * yY;
+    acc[2] += qzz * z0_;
+    acc[3] += px * xX;
+    acc[4] += py * yY;
+    acc[5] += pz * z0_;
+    acc[6] += py * xY;
+    acc[6] += px * yX;
+    acc[7] += pz * x0_;
+    acc[7] += px * zX;
+    acc[8] += pz * y0_;
+    acc[8] += py * zY;
+}
+
+// u1 = j/rho + (g + F^mf)/2 into the padded (rho, u1) array with its images,
+// and F^mf
+template <typename R>
+__device__ __forceinline__ void mf_finish(const Geom &g, const Pad &p, int x, int y, int z, R rr, R Fx, R Fy, R Fz,
+                                          const R *__restrict__ jx, const R *__restrict__ jy,
+                                          const R *__restrict__ jz, R gx, R gy, R gz, V4<R> *__restrict__ ru1_p,
+                                          V4<R> *__restrict__ fmf)
+{
+    const int i = (z * g.ny + y) * g.nx + x;
+    const R inv = R(1) / rr;
+    const V4<R> v = {rr, jx[i] * inv + R(0.5) * (gx + Fx), jy[i] * inv + R(0.5) * (gy + Fy),
                      jz[i] * inv + R(0.5) * (gz + Fz)};
     for_images(g, p, x, y, z, [&](int k) { ru1_p[k] = v; });
     fmf[i] = V4<R>{Fx, Fy, Fz, R(0)};
 }
 
-// ---------------------------------------------------------------------------
-// k_shell: F^v = c_v sum_e k (k.W), A_ij = cA rho sum_e (k_j W_i + k_i W_j),
-// W = gamma_mid rho(r+e) (u1(r+e) - u1(r)).
-// A block owns a TX x TY x TZ tile.  The loop over the shell runs e_z = c
-// from -R to R; for each c the (rho, u1) planes z0+c .. z0+c+TZ-1 of the
-// tile plus an R-wide halo sit in an LDS ring of TZ+1 slots, the next plane
-// is fetched while the current c is summed, and one barrier separates the
-// c-steps.  gamma comes through L1/L2 from the padded array.  Blocks are
-// ordered so that each XCD receives a contiguous run of tiles (shared halos
-// stay in that XCD's L2).
-// ---------------------------------------------------------------------------
-template <typename R, int TX, int TY, int TZ, int NREG>
-__global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, const V4<R> *__restrict__ ru1_p,
-                                                      const R *__restrict__ gam_p, const V4<R> *__restrict__ fmf,
-                                                      const Quad<R> *__restrict__ quads,
-                                                      const int *__restrict__ qstart, R cv, R cA, R gx, R gy, R gz,
-                                                      int smdb, int tiles_x, int tiles_y, int tiles_z,
-                                                      R *__restrict__ Fo, R *__restrict__ Ao)
+// F = rho (g + F^mf + c_v sum k (k.W)) and the traceless SMDB field
+// A = cA rho (sum_e (k_j W_i + k_i W_j)) minus its trace / 3
+template <typename R>
+__device__ __forceinline__ void sh_finish(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
+                                          R gx, R gy, R gz, int smdb, const V4<R> *__restrict__ fmf,
+                                          R *__restrict__ Fo, R *__restrict__ Ao)
 {
-    constexpr int NT = TX * TY * TZ, NS = TZ + 1;
-    extern __shared__ unsigned char lds_raw[];
-    V4<R> *win = reinterpret_cast<V4<R> *>(lds_raw);
-    const int LX = TX + 2 * Rr, LY = TY + 2 * Rr, LP = LX * LY;
-
-    // XCD-aware tile order: hardware block id -> contiguous run per XCD
-    const int nb = tiles_x * tiles_y * tiles_z;
-    const int id = blockIdx.x, xcd = id & 7, qq = nb >> 3, rem = nb & 7;
-    const int lid = (xcd < rem ? xcd * (qq + 1) : rem * (qq + 1) + (xcd - rem) * qq) + (id >> 3);
-    const int x0 = (lid % tiles_x) * TX;
-    const int t1 = lid / tiles_x;
-    const int y0 = (t1 % tiles_y) * TY, z0 = (t1 / tiles_y) * TZ;
-
-    const int tid = threadIdx.x;
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    const bool valid = x < g.nx && y < g.ny && z < g.nz;
-
-    // staging of one (rho, u1) plane of the tile plus halo, NREG float4 per
-    // thread: element e of the plane is (ii, jj) = (e % LX, e / LX); the
-    // offsets are fixed per thread, the plane moves
-    int soff[NREG];
-#pragma unroll
-    for (int k = 0; k < NREG; ++k) {
-        const int e = min(tid + k * NT, LP - 1);
-        const int X = min(max(x0 - Rr + e % LX + p.P, 0), p.PX - 1);
-        const int Y = min(max(y0 - Rr + e / LX + p.P, 0), p.PY - 1);
-        soff[k] = Y * p.PX + X;
-    }
-#define WDLB_FETCH(pz)                                                                  \
-    {                                                                                   \
-        const long long zb_ = (long long)min(max((pz) + p.P, 0), p.PZ - 1) * p.PXY;    \
-        _Pragma("unroll") for (int k_ = 0; k_ < NREG; ++k_) {                           \
-            const V4<R> v_ = ru1_p[zb_ + soff[k_]];                                     \
-            rx[k_] = v_.x;                                                              \
-            ry[k_] = v_.y;                                                              \
-            rz[k_] = v_.z;                                                              \
-            rw[k_] = v_.w;                                                              \
-        }                                                                               \
-    }
-#define WDLB_STORE(sl)                                                                  \
-    {                                                                                   \
-        const int sl_ = (sl);                                                           \
-        _Pragma("unroll") for (int k_ = 0; k_ < NREG; ++k_) {                           \
-            const int e_ = tid + k_ * NT;                                               \
-            if (e_ < LP) win[sl_ * LP + e_] = V4<R>{rx[k_], ry[k_], rz[k_], rw[k_]};    \
-        }                                                                               \
-    }
-    R rx[NREG], ry[NREG], rz[NREG], rw[NREG];
-#pragma unroll
-    for (int pk = 0; pk < TZ; ++pk) {
-        WDLB_FETCH(z0 - Rr + pk);
-        WDLB_STORE(pk);
-    }
-    __syncthreads();
-
-    const int zc = min(z, g.nz - 1), yc = min(y, g.ny - 1), xc = min(x, g.nx - 1);
-    const int gbase = pidx(p, xc, yc, zc);
-    const V4<R> c0 = ru1_p[gbase];
-    const int lbase = (ly + Rr) * LX + (lx + Rr);
-
-    R vx = 0, vy = 0, vz = 0;
-    R axx = 0, ayy = 0, azz = 0, axy = 0, axz = 0, ayz = 0;
-    for (int c = -Rr; c <= Rr; ++c) {
-        const bool more = c < Rr;
-        if (more) WDLB_FETCH(z0 + c + TZ);
-        const V4<R> *pl = win + ((lz + c + Rr) % NS) * LP + lbase;
-        const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
-        for (int q = qb; q < qe; ++q) {
-            const Quad<R> Qd = quads[q];
-            const int a = Qd.a, bb = Qd.b;
-            int so[4], mo[4];
-            quad_offsets(a, bb, Qd.c, p.PX, p.PXY, so, mo);
-            const int lo[4] = {a + bb * LX, -a + bb * LX, a - bb * LX, -a - bb * LX};
-            const R *gb = gam_p + (long long)Qd.hidx * p.NP + gbase;
-            R x0_, xX, xY, xXY, y0_, yX, yY, yXY, z0_, zX, zY;
-            {
-                // mirror products and Hadamard without FMA fusion (exact
-                // zeros for identical mirror images)
-#pragma clang fp contract(off)
-                R Wx[4], Wy[4], Wz[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const V4<R> s = pl[lo[m]];
-                    const R G = gb[mo[m]] * s.x;
-                    Wx[m] = G * (s.y - c0.y);
-                    Wy[m] = G * (s.z - c0.z);
-                    Wz[m] = G * (s.w - c0.w);
-                }
-                // Hadamard transform over the mirror signs (sx, sy)
-                const R xP1 = Wx[0] + Wx[1], xM1 = Wx[0] - Wx[1], xP2 = Wx[2] + Wx[3], xM2 = Wx[2] - Wx[3];
-                const R yP1 = Wy[0] + Wy[1], yM1 = Wy[0] - Wy[1], yP2 = Wy[2] + Wy[3], yM2 = Wy[2] - Wy[3];
-                const R zP1 = Wz[0] + Wz[1], zM1 = Wz[0] - Wz[1], zP2 = Wz[2] + Wz[3], zM2 = Wz[2] - Wz[3];
-                x0_ = xP1 + xP2;
-                xX = xM1 + xM2;
-                xY = xP1 - xP2;
-                xXY = xM1 - xM2;
-                y0_ = yP1 + yP2;
-                yX = yM1 + yM2;
-                yY = yP1 - yP2;
-                yXY = yM1 - yM2;
-                z0_ = zP1 + zP2;
-                zX = zM1 + zM2;
-                zY = zP1 - zP2;
-            }
-            vx += Qd.qxx * x0_ + Qd.qxy * yXY + Qd.qxz * zX;
-            vy += Qd.qxy * xXY + Qd.qyy * y0_ + Qd.qyz * zY;
-            vz += Qd.qxz * xX + Qd.qyz * yY + Qd.qzz * z0_;
-            axx += Qd.px * xX;
-            ayy += Qd.py * yY;
-            azz += Qd.pz * z0_;
-            axy += Qd.py * xY + Qd.px * yX;
-            axz += Qd.pz * x0_ + Qd.px * zX;
-            ayz += Qd.pz * y0_ + Qd.py * zY;
-        }
-        if (more) WDLB_STORE((c + TZ + Rr) % NS);
-        __syncthreads();
-    }
-#undef WDLB_FETCH
-#undef WDLB_STORE
-    if (!valid) return;
     const long long N = g.N;
     const int i = (z * g.ny + y) * g.nx + x;
-    const R r0 = c0.x;
     const V4<R> fm = fmf[i];
-    Fo[i] = r0 * (gx + fm.x + cv * vx);
-    Fo[N + i] = r0 * (gy + fm.y + cv * vy);
-    Fo[2 * N + i] = r0 * (gz + fm.z + cv * vz);
+    Fo[i] = r0 * (gx + fm.x + cv * acc[0]);
+    Fo[N + i] = r0 * (gy + fm.y + cv * acc[1]);
+    Fo[2 * N + i] = r0 * (gz + fm.z + cv * acc[2]);
     R Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
     if (smdb) {
         const R ca = cA * r0;
-        Axx = ca * R(2) * axx;
-        Ayy = ca * R(2) * ayy;
-        Azz = ca * R(2) * azz;
-        Axy = ca * axy;
-        Axz = ca * axz;
-        Ayz = ca * ayz;
+        Axx = ca * R(2) * acc[3];
+        Ayy = ca * R(2) * acc[4];
+        Azz = ca * R(2) * acc[5];
+        Axy = ca * acc[6];
+        Axz = ca * acc[7];
+        Ayz = ca * acc[8];
         const R tr = (Axx + Ayy + Azz) / R(3);
         Axx -= tr;
         Ayy -= tr;
@@ -522,6 +677,229 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
     Ao[3 * N + i] = Axy;
     Ao[4 * N + i] = Axz;
     Ao[5 * N + i] = Ayz;
+}
+
+// gamma of the four mirror images of quad (a, b, c) for the generic kernels:
+// from the gamma ring (GL) or through the caches from the padded arrays
+template <typename R, bool GL>
+__device__ __forceinline__ void gamma_quad(const R *gl, int LG, int LXg, const R *__restrict__ gam_p, const Pad &p,
+                                           int gbase, int a, int b, int c, int hidx, R (&gm)[4])
+{
+    if constexpr (GL) {
+        const int hb = (hidx & 3) * LG, ha = a >> 1, hna = (-a) >> 1;
+        const int hbb = (b >> 1) * LXg, hnb = ((-b) >> 1) * LXg;
+        gm[0] = gl[hb + ha + hbb];
+        gm[1] = gl[hb + hna + hbb];
+        gm[2] = gl[hb + ha + hnb];
+        gm[3] = gl[hb + hna + hnb];
+    } else {
+        int so[4], mo[4];
+        quad_offsets(a, b, c, p.PX, p.PXY, so, mo);
+        const R *gb = gam_p + (long long)hidx * p.NP + gbase;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gm[m] = gb[mo[m]];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_meanfield: F^mf = -kT sigma^2 sum_e k G, G = gamma_mid rho(r+e); then
+// u1 = j/rho + (g + F^mf)/2.  Generic: the shell comes from the quad table.
+// ---------------------------------------------------------------------------
+template <typename R, int TX, int TY, int TZ, int NR, int NG>
+__global__ __launch_bounds__(TX *TY *TZ) void k_meanfield(Geom g, Pad p, int Rr, const R *__restrict__ rho_p,
+                                                          const R *__restrict__ jx, const R *__restrict__ jy,
+                                                          const R *__restrict__ jz, const R *__restrict__ gam_p,
+                                                          const Quad<R> *__restrict__ quads,
+                                                          const int *__restrict__ qstart, R cmf, R gx, R gy, R gz,
+                                                          int tiles_x, int tiles_y, int tiles_z,
+                                                          V4<R> *__restrict__ ru1_p, V4<R> *__restrict__ fmf)
+{
+    constexpr bool GL = NG > 0;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, R, TX, TY, TZ, NR, NG> rg;
+    rg.init(lds_raw, p, Rr, tc, rho_p, gam_p);
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const int LX = rg.pr.LX;
+    R fx = 0, fy = 0, fz = 0;
+    for (int c = -Rr; c <= Rr; ++c) {
+        rg.begin(c, p, rho_p, gam_p);
+        const R *pl = rg.plane(c);
+        const R *gl = GL ? rg.gamma(c) : nullptr;
+        const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
+        for (int q = qb; q < qe; ++q) {
+            const Quad<R> Qd = quads[q];
+            const int a = Qd.a, b = Qd.b;
+            R gm[4], rm[4];
+            gamma_quad<R, GL>(gl, rg.gr.LG, rg.gr.LXg, gam_p, p, gbase, a, b, Qd.c, Qd.hidx, gm);
+            rm[0] = pl[a + b * LX];
+            rm[1] = pl[-a + b * LX];
+            rm[2] = pl[a - b * LX];
+            rm[3] = pl[-a - b * LX];
+            mf_quad<R>(gm, rm, Qd.px, Qd.py, Qd.pz, fx, fy, fz);
+        }
+        rg.end(c);
+    }
+    if (!valid) return;
+    mf_finish<R>(g, p, x, y, z, rho_p[gbase], cmf * fx, cmf * fy, cmf * fz, jx, jy, jz, gx, gy, gz, ru1_p, fmf);
+}
+
+// ---------------------------------------------------------------------------
+// k_shell: F^v = c_v sum_e k (k.W), A_ij = cA rho sum_e (k_j W_i + k_i W_j),
+// W = gamma_mid rho(r+e) (u1(r+e) - u1(r)); the dominant kernel.  Generic:
+// the shell comes from the quad table.
+// ---------------------------------------------------------------------------
+template <typename R, int TX, int TY, int TZ, int NR, int NG>
+__global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, const V4<R> *__restrict__ ru1_p,
+                                                      const R *__restrict__ gam_p, const V4<R> *__restrict__ fmf,
+                                                      const Quad<R> *__restrict__ quads,
+                                                      const int *__restrict__ qstart, R cv, R cA, R gx, R gy, R gz,
+                                                      int smdb, int tiles_x, int tiles_y, int tiles_z,
+                                                      R *__restrict__ Fo, R *__restrict__ Ao)
+{
+    constexpr bool GL = NG > 0;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, V4<R>, TX, TY, TZ, NR, NG> rg;
+    rg.init(lds_raw, p, Rr, tc, ru1_p, gam_p);
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const V4<R> c0 = ru1_p[gbase];
+    const int LX = rg.pr.LX;
+    R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = -Rr; c <= Rr; ++c) {
+        rg.begin(c, p, ru1_p, gam_p);
+        const V4<R> *pl = rg.plane(c);
+        const R *gl = GL ? rg.gamma(c) : nullptr;
+        const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
+        for (int q = qb; q < qe; ++q) {
+            const Quad<R> Qd = quads[q];
+            const int a = Qd.a, b = Qd.b;
+            R gm[4];
+            V4<R> sm[4];
+            gamma_quad<R, GL>(gl, rg.gr.LG, rg.gr.LXg, gam_p, p, gbase, a, b, Qd.c, Qd.hidx, gm);
+            sm[0] = pl[a + b * LX];
+            sm[1] = pl[-a + b * LX];
+            sm[2] = pl[a - b * LX];
+            sm[3] = pl[-a - b * LX];
+            sh_quad<R>(gm, sm, c0, Qd.px, Qd.py, Qd.pz, Qd.qxx, Qd.qyy, Qd.qzz, Qd.qxy, Qd.qxz, Qd.qyz, acc);
+        }
+        rg.end(c);
+    }
+    if (!valid) return;
+    sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
+}
+
+// ---------------------------------------------------------------------------
+// The same two kernels specialised for the shell of 2 sigma = S2 (rings in
+// LDS only): the e_z steps and the quads are unrolled at compile time, so
+// every LDS offset is an immediate and every weight a literal.  Offsets are
+// taken from the corner of each lane's stencil window (non-negative).
+// ---------------------------------------------------------------------------
+// The sums of a c-step are finished before its barrier: an empty asm that
+// reads and writes the accumulator keeps the compiler from sinking the
+// arithmetic of every c-step to the end of the kernel (which would keep all
+// loaded operands of the whole shell live at once).  It emits no code.
+__device__ __forceinline__ void pin(float &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+template <int B, typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, B + I>{}), ...);
+}
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (E > B) static_for_seq<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+
+template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
+__global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const R *__restrict__ rho_p,
+                                                            const R *__restrict__ jx, const R *__restrict__ jy,
+                                                            const R *__restrict__ jz, const R *__restrict__ gam_p,
+                                                            R cmf, R gx, R gy, R gz, int tiles_x, int tiles_y,
+                                                            int tiles_z, V4<R> *__restrict__ ru1_p,
+                                                            V4<R> *__restrict__ fmf)
+{
+    static_assert(NG > 0, "specialised shell kernels stage gamma in LDS");
+    using SH = Shell<S2>;
+    constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, R, TX, TY, TZ, NR, NG> rg;
+    rg.init(lds_raw, p, RC, tc, rho_p, gam_p);
+    R fx = 0, fy = 0, fz = 0;
+    static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
+        constexpr int c = decltype(ci)::value;
+        rg.begin(c, p, rho_p, gam_p);
+        const R *pc = rg.plane(c) - (RC + RC * LX);
+        const R *gc = rg.gamma(c) - (O + O * LXg);
+        static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
+            constexpr CQuad Q = SH::T.q[decltype(qi)::value];
+            constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
+            constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
+                          gnb = (O + ((-b) >> 1)) * LXg;
+            const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+            const R rm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                             pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+            mf_quad<R>(gm, rm, R(Q.px), R(Q.py), R(Q.pz), fx, fy, fz);
+        });
+        pin(fx);
+        pin(fy);
+        pin(fz);
+        rg.end(c);
+    });
+    if (!valid) return;
+    mf_finish<R>(g, p, x, y, z, rho_p[pidx(p, x, y, z)], cmf * fx, cmf * fy, cmf * fz, jx, jy, jz, gx, gy, gz,
+                 ru1_p, fmf);
+}
+
+template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
+__global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<R> *__restrict__ ru1_p,
+                                                        const R *__restrict__ gam_p, const V4<R> *__restrict__ fmf,
+                                                        R cv, R cA, R gx, R gy, R gz, int smdb, int tiles_x,
+                                                        int tiles_y, int tiles_z, R *__restrict__ Fo,
+                                                        R *__restrict__ Ao)
+{
+    static_assert(NG > 0, "specialised shell kernels stage gamma in LDS");
+    using SH = Shell<S2>;
+    constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, V4<R>, TX, TY, TZ, NR, NG> rg;
+    rg.init(lds_raw, p, RC, tc, ru1_p, gam_p);
+    const V4<R> c0 = ru1_p[pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1))];
+    R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
+        constexpr int c = decltype(ci)::value;
+        rg.begin(c, p, ru1_p, gam_p);
+        const V4<R> *pc = rg.plane(c) - (RC + RC * LX);
+        const R *gc = rg.gamma(c) - (O + O * LXg);
+        static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
+            constexpr CQuad Q = SH::T.q[decltype(qi)::value];
+            constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
+            constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
+                          gnb = (O + ((-b) >> 1)) * LXg;
+            const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+            const V4<R> sm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                                 pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+            sh_quad<R>(gm, sm, c0, R(Q.px), R(Q.py), R(Q.pz), R(Q.qxx), R(Q.qyy), R(Q.qzz), R(Q.qxy), R(Q.qxz),
+                       R(Q.qyz), acc);
+        });
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pin(acc[k]);
+        rg.end(c);
+    });
+    if (!valid) return;
+    sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
 }
 
 // F (3N) and A (xx, yy, zz, xy, xz, yz; 6N) for nonlocal = 0: F = rho g

@@ -50,7 +50,9 @@ struct wdlb_ctx {
     int *ball;
     int nq, nball, reach;
     double wS;         // 4 pi / |S|
-    int tile;          // k_shell tile variant
+    int tile;          // contact-shell tile variant (index into SHELL_TILES)
+    int tile_req;      // requested variant, -1 = automatic
+    int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
     int cur;
     int64_t step;
     bool inited;
@@ -194,39 +196,65 @@ std::vector<Quad<R>> build_quads(double sigma, int &nshell)
             for (int a = 0; a <= R_; ++a) {
                 double r2 = double(a * a + b * b + c * c);
                 if (!(r2 >= lo && r2 < hi)) continue;
-                double len = std::sqrt(r2);
-                double ax = a / len, ay = b / len, az = c / len;
-                double w = (a > 0 ? 1.0 : 0.5) * (b > 0 ? 1.0 : 0.5);
+                const CQuad cq = make_cquad(a, b, c);
                 Quad<R> q;
-                q.a = a;
-                q.b = b;
-                q.c = c;
-                q.hidx = (a & 1) | ((b & 1) << 1) | ((c & 1) << 2);
-                q.px = R(w * ax);
-                q.py = R(w * ay);
-                q.pz = R(w * az);
-                q.qxx = R(w * ax * ax);
-                q.qyy = R(w * ay * ay);
-                q.qzz = R(w * az * az);
-                q.qxy = R(w * ax * ay);
-                q.qxz = R(w * ax * az);
-                q.qyz = R(w * ay * az);
+                q.a = cq.a;
+                q.b = cq.b;
+                q.c = cq.c;
+                q.hidx = cq.h;
+                q.px = R(cq.px);
+                q.py = R(cq.py);
+                q.pz = R(cq.pz);
+                q.qxx = R(cq.qxx);
+                q.qyy = R(cq.qyy);
+                q.qzz = R(cq.qzz);
+                q.qxy = R(cq.qxy);
+                q.qxz = R(cq.qxz);
+                q.qyz = R(cq.qyz);
                 q.pad0 = q.pad1 = q.pad2 = R(0);
                 v.push_back(q);
             }
     return v;
 }
 
-// k_shell tile variants: 16x16x2 tiles (3 ring slots, 512 threads) with 2,
-// 3 or 4 staged float4 per thread, else 16x16x1 (2 slots, 256 threads) with
-// up to 10; the first that fits is used
-int pick_tile(int reach, size_t v4)
+// Contact-shell tile variants (k_meanfield and k_shell use the same one),
+// tried in this order: 32 x 8 x 2 tiles with both LDS rings for growing
+// reach, a 32 x 16 x 1 tile, and a 16 x 16 x 1 tile that reads gamma through
+// L1/L2 (NG = 0).  NR / NG are the plane / gamma-slice elements each thread
+// stages.
+struct ShellTile {
+    int TX, TY, TZ, NR, NG;
+};
+constexpr ShellTile SHELL_TILES[] = {{32, 8, 2, 2, 5}, {32, 8, 2, 3, 6}, {32, 8, 2, 4, 8}, {32, 16, 1, 7, 13},
+                                     {16, 16, 1, 10, 0}};
+constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
+static_assert(NTILES == WDLB_NTILES, "the header's variant count");
+constexpr size_t LDS_MAX = 160 * 1024;
+
+constexpr bool tile_fits(const ShellTile &t, int reach, size_t rbytes)
 {
-    const size_t LP = (16 + 2 * (size_t)reach) * (16 + 2 * (size_t)reach);
-    const int n0 = (int)((LP + 511) / 512), n1 = (int)((LP + 255) / 256);
-    if (3 * LP * v4 <= 96 * 1024 && n0 <= 4) return n0 <= 2 ? 0 : (n0 == 3 ? 1 : 2);
-    if (2 * LP * v4 <= 160 * 1024 && n1 <= 10) return 3;
+    const int NT = t.TX * t.TY * t.TZ;
+    const int LP = (t.TX + 2 * reach) * (t.TY + 2 * reach), LS = 4 * (t.TX + reach) * (t.TY + reach);
+    if ((LP + NT - 1) / NT > t.NR) return false;
+    if (t.NG > 0 && (LS + NT - 1) / NT > t.NG) return false;
+    return shell_lds_bytes(t.TX, t.TY, t.TZ, reach, 4 * rbytes, rbytes, t.NG > 0) <= LDS_MAX;
+}
+
+constexpr int pick_tile(int reach, size_t rbytes)
+{
+    for (int k = 0; k < NTILES; ++k)
+        if (tile_fits(SHELL_TILES[k], reach, rbytes)) return k;
     return -1;
+}
+
+// 2 sigma when the library holds shell kernels specialised for sigma
+// (those of the tile the automatic choice takes), else 0
+int specialised_s2(double sigma)
+{
+    static const int S2[] = {6, 8, 12, 16, 20};
+    for (int s2 : S2)
+        if (sigma == 0.5 * s2) return s2;
+    return 0;
 }
 
 template <typename R>
@@ -248,7 +276,15 @@ wdlb_status upload_tables(wdlb_ctx *c)
                 if (4.0 * (x * x + y * y + z * z) <= c->prm.sigma * c->prm.sigma)
                     b.push_back(x + y * c->pad.PX + z * c->pad.PXY);
     if ((int)b.size() > MAX_BALL) return fail(c, WDLB_E_INVAL, "stencil too large");
-    c->tile = pick_tile(reach, 4 * sizeof(R));
+    c->spec_s2 = 0;
+    if (c->tile_req >= 0) {
+        if (!tile_fits(SHELL_TILES[c->tile_req], reach, sizeof(R)))
+            return fail(c, WDLB_E_INVAL, "the requested shell tile does not fit this sigma");
+        c->tile = c->tile_req;
+    } else {
+        c->tile = pick_tile(reach, sizeof(R));
+        if (c->tile >= 0 && SHELL_TILES[c->tile].NG > 0) c->spec_s2 = specialised_s2(c->prm.sigma);
+    }
     if (c->tile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the shell tiles");
     HIPCHK(c, hipMemcpyAsync(c->quads, q.data(), q.size() * sizeof(Quad<R>), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->qstart, qs.data(), qs.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -321,24 +357,96 @@ wdlb_status launch(wdlb_ctx *c, int k, L &&fn)
     return WDLB_OK;
 }
 
-template <typename R, int TX, int TY, int TZ, int NREG>
-wdlb_status launch_shell(wdlb_ctx *c)
+template <typename R, int TX, int TY, int TZ, int NR, int NG>
+wdlb_status launch_shell_pair(wdlb_ctx *c)
 {
     const Geom g = c->g;
     const wdlb_params &p = c->prm;
     const double s = p.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
-    const int LX = TX + 2 * c->reach, LY = TY + 2 * c->reach;
-    const size_t lds = (size_t)(TZ + 1) * LX * LY * sizeof(V4<R>);
-    auto kern = k_shell<R, TX, TY, TZ, NREG>;
-    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    return launch(c, K_SHELL, [&] {
-        hipLaunchKernelGGL(kern, dim3(tx * ty * tz), dim3(TX * TY * TZ), lds, c->stream, g, c->pad, c->reach,
-                           (const V4<R> *)c->ru1_p, (const R *)c->gam_p, (const V4<R> *)c->fmf,
-                           (const Quad<R> *)c->quads, (const int *)c->qstart,
-                           R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]),
-                           R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A);
+    const dim3 grid(tx * ty * tz), block(TX * TY * TZ);
+    const size_t lmf = shell_lds_bytes(TX, TY, TZ, c->reach, sizeof(R), sizeof(R), NG > 0);
+    const size_t lsh = shell_lds_bytes(TX, TY, TZ, c->reach, sizeof(V4<R>), sizeof(R), NG > 0);
+    auto kmf = k_meanfield<R, TX, TY, TZ, NR, NG>;
+    auto ksh = k_shell<R, TX, TY, TZ, NR, NG>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
+    HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
+    wdlb_status st = launch(c, K_MEANFIELD, [&] {
+        hipLaunchKernelGGL(kmf, grid, block, lmf, c->stream, g, c->pad, c->reach, (const R *)c->rho_p,
+                           (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p,
+                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(-KT * s * s), R(p.g[0]),
+                           R(p.g[1]), R(p.g[2]), tx, ty, tz, (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
     });
+    if (st != WDLB_OK) return st;
+    return launch(c, K_SHELL, [&] {
+        hipLaunchKernelGGL(ksh, grid, block, lsh, c->stream, g, c->pad, c->reach, (const V4<R> *)c->ru1_p,
+                           (const R *)c->gam_p, (const V4<R> *)c->fmf, (const Quad<R> *)c->quads,
+                           (const int *)c->qstart, R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s),
+                           R(p.g[0]), R(p.g[1]), R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A);
+    });
+}
+
+// the pair specialised for the shell 2 sigma = S2 on the tile that the
+// automatic choice takes for it
+template <typename R, int S2>
+wdlb_status launch_shell_pair_s(wdlb_ctx *c)
+{
+    constexpr int RC = Shell<S2>::R;
+    constexpr int TI = pick_tile(RC, sizeof(R));
+    static_assert(TI >= 0, "no tile for this shell");
+    constexpr ShellTile T = SHELL_TILES[TI];
+    constexpr int TX = T.TX, TY = T.TY, TZ = T.TZ, NR = T.NR, NG = T.NG;
+    if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
+    if constexpr (NG == 0) {
+        return launch_shell_pair<R, TX, TY, TZ, NR, NG>(c);
+    } else {
+        const Geom g = c->g;
+        const wdlb_params &p = c->prm;
+        const double s = p.sigma;
+        const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+        const dim3 grid(tx * ty * tz), block(TX * TY * TZ);
+        const size_t lmf = shell_lds_bytes(TX, TY, TZ, RC, sizeof(R), sizeof(R), true);
+        const size_t lsh = shell_lds_bytes(TX, TY, TZ, RC, sizeof(V4<R>), sizeof(R), true);
+        auto kmf = k_meanfield_s<R, S2, TX, TY, TZ, NR, NG>;
+        auto ksh = k_shell_s<R, S2, TX, TY, TZ, NR, NG>;
+        HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
+        HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
+        wdlb_status st = launch(c, K_MEANFIELD, [&] {
+            hipLaunchKernelGGL(kmf, grid, block, lmf, c->stream, g, c->pad, (const R *)c->rho_p, (const R *)c->jx,
+                               (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p, R(-KT * s * s), R(p.g[0]),
+                               R(p.g[1]), R(p.g[2]), tx, ty, tz, (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
+        });
+        if (st != WDLB_OK) return st;
+        return launch(c, K_SHELL, [&] {
+            hipLaunchKernelGGL(ksh, grid, block, lsh, c->stream, g, c->pad, (const V4<R> *)c->ru1_p,
+                               (const R *)c->gam_p, (const V4<R> *)c->fmf, R(2.0 * s * s * std::sqrt(KT / M_PI)),
+                               R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]), R(p.g[2]), p.smdb, tx, ty, tz,
+                               (R *)c->F, (R *)c->A);
+        });
+    }
+}
+
+template <typename R>
+wdlb_status launch_shells(wdlb_ctx *c)
+{
+    if (c->spec_s2 > 0) {
+        switch (c->spec_s2) {
+        case 6: return launch_shell_pair_s<R, 6>(c);
+        case 8: return launch_shell_pair_s<R, 8>(c);
+        case 12: return launch_shell_pair_s<R, 12>(c);
+        case 16: return launch_shell_pair_s<R, 16>(c);
+        case 20: return launch_shell_pair_s<R, 20>(c);
+        default: break;
+        }
+    }
+    static_assert(NTILES == 5, "one case per entry of SHELL_TILES");
+    switch (c->tile) {
+    case 0: return launch_shell_pair<R, 32, 8, 2, 2, 5>(c);
+    case 1: return launch_shell_pair<R, 32, 8, 2, 3, 6>(c);
+    case 2: return launch_shell_pair<R, 32, 8, 2, 4, 8>(c);
+    case 3: return launch_shell_pair<R, 32, 16, 1, 7, 13>(c);
+    default: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
+    }
 }
 
 // one pass of the step kernels on the current buffers; READ stops after the
@@ -372,19 +480,7 @@ wdlb_status run_pass(wdlb_ctx *c)
                                R(M_PI * s * s * s / 6.0), R(c->wS), (R *)c->gam_p, c->flag);
         });
         if (st != WDLB_OK) return st;
-        st = launch(c, K_MEANFIELD, [&] {
-            hipLaunchKernelGGL((k_meanfield<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->rho_p,
-                               (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p,
-                               (const Quad<R> *)c->quads, c->nq, R(-KT * s * s), R(p.g[0]), R(p.g[1]), R(p.g[2]),
-                               (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
-        });
-        if (st != WDLB_OK) return st;
-        switch (c->tile) {
-        case 0: st = launch_shell<R, 16, 16, 2, 2>(c); break;
-        case 1: st = launch_shell<R, 16, 16, 2, 3>(c); break;
-        case 2: st = launch_shell<R, 16, 16, 2, 4>(c); break;
-        default: st = launch_shell<R, 16, 16, 1, 10>(c);
-        }
+        st = launch_shells<R>(c);
         if (st != WDLB_OK) return st;
     } else {
         st = launch(c, K_SHELL, [&] {
@@ -530,6 +626,7 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->cur = 0;
     c->step = 0;
     c->inited = false;
+    c->tile_req = -1;
     wdlb_status st = tables(c);
     if (st != WDLB_OK) {
         delete c;
@@ -823,6 +920,29 @@ wdlb_status wdlb_profile_read(wdlb_ctx *c, int32_t kernel, double *total_ms, int
     if (st != WDLB_OK) return st;
     if (total_ms) *total_ms = c->prof_ms[kernel];
     if (launches) *launches = c->prof_n[kernel];
+    return WDLB_OK;
+}
+
+wdlb_status wdlb_set_tile(wdlb_ctx *c, int32_t variant)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (variant < -1 || variant >= WDLB_NTILES) return fail(c, WDLB_E_INVAL, "tile variant out of range");
+    const int old = c->tile_req;
+    c->tile_req = variant;
+    wdlb_status st = tables(c);
+    if (st != WDLB_OK) {
+        c->tile_req = old;
+        tables(c);
+        return fail(c, st, "the requested shell tile does not fit this sigma");
+    }
+    return WDLB_OK;
+}
+
+wdlb_status wdlb_get_tile(wdlb_ctx *c, int32_t *variant, int32_t *specialised)
+{
+    if (!c || !variant) return WDLB_E_INVAL;
+    *variant = c->tile;
+    if (specialised) *specialised = c->spec_s2 > 0 ? 1 : 0;
     return WDLB_OK;
 }
 

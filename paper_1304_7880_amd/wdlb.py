@@ -19,6 +19,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_NOT_CONVERGED = range(7)
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSTABLE", 5: "E_STATE", 6: "E_NOT_CONVERGED"}
 FP64, FP32, BF16_NEQ = 0, 1, 2
 NKERNELS = 6
+NTILES = 5
 PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ}
 
 # D3Q19 order of the library's populations (include/wdlb.h)
@@ -29,8 +30,8 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
            "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
-           "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_last_error",
-           "wdlb_destroy"]
+           "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
+           "wdlb_get_tile", "wdlb_last_error", "wdlb_destroy"]
 
 
 class LatticeDesc(C.Structure):
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH):
     L.wdlb_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
     L.wdlb_kernel_name.argtypes = [C.c_int32]
     L.wdlb_kernel_name.restype = C.c_char_p
+    L.wdlb_set_tile.argtypes = [vp, C.c_int32]
+    L.wdlb_get_tile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.wdlb_last_error.argtypes = [vp]
     L.wdlb_last_error.restype = C.c_char_p
     L.wdlb_destroy.argtypes = [vp]
@@ -229,6 +232,16 @@ class Context:
             self._chk(self._L.wdlb_profile_read(self.h, k, C.byref(ms), C.byref(n)), "profile_read")
             out[self._L.wdlb_kernel_name(k).decode()] = (ms.value, n.value)
         return out
+
+    def set_tile(self, variant=-1):
+        """Contact-shell tile variant (0 .. NTILES-1), -1 = automatic."""
+        self._chk(self._L.wdlb_set_tile(self.h, int(variant)), "set_tile")
+
+    def get_tile(self):
+        """(tile variant in use, True when the compiled-shell kernels run)."""
+        v, sp = C.c_int32(), C.c_int32()
+        self._chk(self._L.wdlb_get_tile(self.h, C.byref(v), C.byref(sp)), "get_tile")
+        return v.value, bool(sp.value)
 
     def get_step(self):
         s = C.c_int64()

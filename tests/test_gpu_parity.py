@@ -73,6 +73,79 @@ def test_random_fields_few_steps(case, prec, tol):
     ctx.destroy()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("variant", range(5))
+def test_shell_tile_variants(variant, prec, tol):
+    """Every contact-shell tile variant (LDS rings of 32x8x2, 32x16x1 and the
+    16x16x1 tile reading gamma through the caches), forced on a walled
+    40x20x13 lattice that leaves ragged tiles in x, y and z."""
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma, eta, tau, g = 40, 20, 13, 4.0, 0.3, 0.9, (1e-4, -3e-5, 0.0)
+    _say(f"tile variant {variant} {prec}")
+    n0 = packing_to_density(eta, sigma)
+    n, u = random_fields(nx, ny, nz, n0, 0.05, 0.01, seed=11)
+    st = ref.State.from_fields(ref.Config(nx, ny, nz, True, sigma, tau, g), n, u)
+    ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, g)
+    ctx.set_tile(variant)
+    assert ctx.get_tile() == (variant, False)
+    ctx.init_fields(n, u)
+    for k in range(3):
+        rho_o, u_o, F_o, A_o = st.fields()
+        rho_g, u_g, F_g, A_g = ctx.read_fields(with_forces=True)
+        assert _rel(rho_g, rho_o) < tol, ("rho", k)
+        assert _rel(u_g, u_o) < tol, ("u", k)
+        assert _rel(F_g, F_o) < 10 * tol, ("F", k)
+        assert _rel(A_g, A_o) < 10 * tol, ("A0", k)
+        st.step(1)
+        ctx.step(1)
+    ctx.set_tile(-1)
+    ctx.destroy()
+
+
+def test_shell_tile_that_does_not_fit_is_refused():
+    """sigma = 16 in FP64: the 32x8x2 LDS rings exceed 160 KB; forcing that
+    variant fails and leaves the automatic choice in place."""
+    from paper_1304_7880_amd import wdlb
+    ctx = _ctx(8, 8, 40, True, "fp64", 16.0, 0.2, 1.0, (0, 0, 0))
+    auto = ctx.get_tile()
+    with pytest.raises(wdlb.WdlbError):
+        ctx.set_tile(0)
+    assert ctx.get_tile() == auto
+    ctx.destroy()
+
+
+SPECIALISED = [3.0, 4.0, 6.0, 8.0, 10.0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("sigma", SPECIALISED)
+def test_compiled_shell_equals_table_driven(sigma, prec):
+    """The kernels compiled for one shell and the table-driven kernels on the
+    same tile sum the same terms in the same order: identical results, bit
+    for bit, on a walled lattice with ragged tiles."""
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, eta, tau, g = 37, 19, 2 * int(sigma) + 9, 0.3, 0.85, (1e-4, 2e-5, -1e-5)
+    _say(f"compiled shell sigma={sigma} {prec}")
+    n0 = packing_to_density(eta, sigma)
+    n, u = random_fields(nx, ny, nz, n0, 0.05, 0.01, seed=5)
+    out = []
+    for forced in (False, True):
+        ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, g)
+        tile, spec = ctx.get_tile()
+        if forced:
+            ctx.set_tile(tile)
+            assert ctx.get_tile() == (tile, False)
+        else:
+            # FP64 at sigma = 10 only fits the tile that reads gamma through the caches
+            assert spec == (prec == "fp32" or sigma < 10), (tile, spec)
+        ctx.init_fields(n, u)
+        ctx.step(3)
+        out.append(ctx.read_fields(with_forces=True))
+        ctx.destroy()
+    for k, name in enumerate(("rho", "u", "F", "A0")):
+        assert np.array_equal(out[0][k], out[1][k]), (name, _rel(out[0][k], out[1][k]))
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_small_slab_full_run(prec, tol):
     """The 4x4x16 slit (sigma = 4, eta = 0.2, tau = 1, g_x = 1e-6), 2000 steps:
