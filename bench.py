@@ -44,26 +44,26 @@ def shell_flops_per_node(sigma: float) -> float:
     return 36.0 * shell_size(sigma)
 
 
-def shell_source_hash() -> str:
-    """sha256 (16 hex) of the k_shell kernel source, to tie counter data to it."""
+def device_source_hash() -> str:
+    """sha256 (16 hex) of the device sources, to tie counter data to them."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_1304_7880_amd", "csrc", "kernels.hpp")).read()
-    a = src.index("template <typename R, int TX, int TY, int TZ, int NREG>")
-    b = src.index("\n}\n", a) + 3
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("d3q19.hpp", "shell.hpp", "kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1304_7880_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
     """Calibrated HBM bytes per k_shell launch from the rocprofv3 counter runs
-    summarised in profiles/, or None if k_shell changed since they were taken."""
+    summarised in profiles/, or None if the device code changed since."""
     path = os.path.join(ROOT, "profiles", "k_shell_slab64.md")
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0].strip() in ("k_shell_traffic_bytes_per_launch", "k_shell_source_sha256_16"):
+        if ":" in line and line.split(":")[0].strip() in ("k_shell_traffic_bytes_per_launch", "device_source_sha256_16"):
             kv[line.split(":")[0].strip()] = line.split(":", 1)[1].strip()
-    if kv.get("k_shell_source_sha256_16") != shell_source_hash():
+    if kv.get("device_source_sha256_16") != device_source_hash():
         return None
     return float(kv["k_shell_traffic_bytes_per_launch"])
 

@@ -153,7 +153,7 @@ wdlb_status wdlb_get_step(const wdlb_ctx *ctx, int64_t *step);
  * synchronises and returns, for kernel id k (0 .. WDLB_NKERNELS-1), the
  * summed device time in milliseconds and the number of launches timed.
  * wdlb_kernel_name(k) names the kernel ("" for an unknown id). */
-#define WDLB_NKERNELS 6
+#define WDLB_NKERNELS 5
 wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t enable);
 wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 const char *wdlb_kernel_name(int32_t kernel);

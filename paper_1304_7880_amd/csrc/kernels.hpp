@@ -4,9 +4,10 @@
 // One step (Sec. 5 of the paper, steps 2-4) is six kernels:
 //   k_moments    pull-stream the stored populations; density (padded array,
 //                with periodic images) and momentum
-//   k_ball       Fischer-Methfessel smoothed density nbar, ball |e| <= sigma/2
-//   k_gamma      Carnahan-Starling contact value at the 8 half-lattice
-//                midpoints of every node, gamma_h(r) = g_CS(nbar(r + h/2))
+//   k_density    Fischer-Methfessel smoothed density nbar (ball
+//                |e| <= sigma/2) and the Carnahan-Starling contact value at
+//                the 8 half-lattice midpoints of every node,
+//                gamma_h(r) = g_CS(nbar(r + h/2)); nbar stays in LDS
 //   k_meanfield  contact-shell sum of the mean-field force F^mf, and the
 //                velocity u1 = j/rho + (g + F^mf)/2 with which F^v and A_ij
 //                are formed
@@ -17,7 +18,7 @@
 //                post-collision populations are streamed by the next pull,
 //                with half-way bounce-back at the walls
 //
-// Padded arrays.  rho, nbar, gamma and (rho, u1) live in arrays padded by P
+// Padded arrays.  rho, gamma and (rho, u1) live in arrays padded by P
 // (the contact-shell reach) on every side.  The kernel that writes a node
 // also writes its periodic images into the padding; beyond a wall the
 // padding stays zero, so rho = u = 0 outside the slit needs no test.  Every
@@ -111,6 +112,34 @@ __device__ __forceinline__ bool node_of(const Geom &g, long long i, int &x, int 
     y = t % g.ny;
     z = t / g.ny;
     return true;
+}
+
+// XCD-aware tile order: consecutive hardware block ids go to different XCDs
+// (round robin), so block id -> tile index gives each XCD a contiguous run of
+// tiles and the halos they share stay in that XCD's L2
+__device__ __forceinline__ int xcd_tile(int id, int nb)
+{
+    const int xcd = id & 7, qq = nb >> 3, rem = nb & 7;
+    return (xcd < rem ? xcd * (qq + 1) : rem * (qq + 1) + (xcd - rem) * qq) + (id >> 3);
+}
+
+struct TileCoord {
+    int x0, y0, z0, lx, ly, lz;
+};
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int tiles_z)
+{
+    TileCoord t;
+    const int lid = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
+    const int t1 = lid / tiles_x;
+    t.x0 = (lid % tiles_x) * TX;
+    t.y0 = (t1 % tiles_y) * TY;
+    t.z0 = (t1 / tiles_y) * TZ;
+    t.lx = threadIdx.x % TX;
+    t.ly = (threadIdx.x / TX) % TY;
+    t.lz = threadIdx.x / (TX * TY);
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -245,44 +274,63 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, Pad p, const V4<R> *__r
     jz[i] = R(c);
 }
 
-// nbar(r) = (1/|B|) sum over the ball of rho; boff[] = padded offsets
-template <typename R>
-__global__ __launch_bounds__(256) void k_ball(Geom g, Pad p, const R *__restrict__ rho_p,
-                                              const int *__restrict__ boff, int nball, R inv_nball,
-                                              R *__restrict__ nbar_p)
+// The sums of a c-step are finished before its barrier: an empty asm that
+// reads and writes the accumulator keeps the compiler from sinking the
+// arithmetic of every c-step to the end of the kernel (which would keep all
+// loaded operands of the whole shell live at once).  It emits no code.
+__device__ __forceinline__ void pin(float &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+template <int B, typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
-    const R *base = rho_p + pidx(p, x, y, z);
-    // four interleaved partial sums keep several gathers in flight; every
-    // node uses the same order, so x,y-uniform states stay exactly uniform
-    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    int q = 0;
-    for (; q + 4 <= nball; q += 4) {
-        s0 += base[boff[q]];
-        s1 += base[boff[q + 1]];
-        s2 += base[boff[q + 2]];
-        s3 += base[boff[q + 3]];
-    }
-    for (; q < nball; ++q) s0 += base[boff[q]];
-    const R v = ((s0 + s1) + (s2 + s3)) * inv_nball;
-    for_images(g, p, x, y, z, [&](int k) { nbar_p[k] = v; });
+    (f(std::integral_constant<int, B + I>{}), ...);
+}
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (E > B) static_for_seq<B>(f, std::make_integer_sequence<int, E - B>{});
 }
 
-// gamma_h(r) = (4 pi/|S|) g_CS(pi sigma^3 nbar_mid / 6), nbar_mid the mean of
-// nbar over the 2^|h| lattice nodes of r + h/2 (outside the slit nbar = 0)
-template <typename R>
-__global__ __launch_bounds__(256) void k_gamma(Geom g, Pad p, const R *__restrict__ nbar_p, R eta_per_n, R wS,
-                                               R *__restrict__ gam_p, int *flag)
+// ---------------------------------------------------------------------------
+// k_density: the smoothed density and the contact values in one pass over
+// TX x TY x TZ tiles.  LDS holds rho over the tile plus the ball reach rb on
+// every side and one more node on the high side of each axis; nbar is formed
+// there for the tile plus that extra layer (the 2^3 corners of every
+// half-lattice point), then gamma_h for the tile's nodes.  nbar never goes
+// to memory.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr size_t density_lds_bytes(int TX, int TY, int TZ, int rb, size_t rbytes)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
-    const int b = pidx(p, x, y, z);
-    const R n000 = nbar_p[b], n100 = nbar_p[b + 1], n010 = nbar_p[b + p.PX], n110 = nbar_p[b + p.PX + 1];
-    const R n001 = nbar_p[b + p.PXY], n101 = nbar_p[b + p.PXY + 1], n011 = nbar_p[b + p.PXY + p.PX],
-            n111 = nbar_p[b + p.PXY + p.PX + 1];
+    return ((size_t)(TX + 2 * rb + 1) * (TY + 2 * rb + 1) * (TZ + 2 * rb + 1) + (size_t)(TX + 1) * (TY + 1) * (TZ + 1)) *
+           rbytes;
+}
+
+// rho over the tile, the ball reach and one extra node (from the padded
+// array: images and zeros beyond the walls are in place)
+template <typename R, int NT>
+__device__ __forceinline__ void density_fill(const TileCoord &tc, const Pad &p, int rb, int LX, int LY, int LZ,
+                                             const R *__restrict__ rho_p, R *win)
+{
+    for (int e = threadIdx.x; e < LX * LY * LZ; e += NT) {
+        const int ix = e % LX, t = e / LX, iy = t % LY, iz = t / LY;
+        const int X = min(max(tc.x0 - rb + ix + p.P, 0), p.PX - 1);
+        const int Y = min(max(tc.y0 - rb + iy + p.P, 0), p.PY - 1);
+        const int Z = min(max(tc.z0 - rb + iz + p.P, 0), p.PZ - 1);
+        win[e] = rho_p[(long long)Z * p.PXY + (long long)Y * p.PX + X];
+    }
+}
+
+// gamma_h of the lane's node from nbar at the 8 corners of its half-lattice
+// points (m0: nbar of the node in the (TX+1)(TY+1)(TZ+1) block), written
+// with the node's periodic images
+template <typename R, int TX, int TY>
+__device__ __forceinline__ void density_gamma(const Geom &g, const Pad &p, int x, int y, int z, const R *m0,
+                                              R eta_per_n, R wS, R *__restrict__ gam_p, int *flag)
+{
+    constexpr int DX = 1, DY = TX + 1, DZ = (TX + 1) * (TY + 1);
+    const R n000 = m0[0], n100 = m0[DX], n010 = m0[DY], n110 = m0[DX + DY];
+    const R n001 = m0[DZ], n101 = m0[DZ + DX], n011 = m0[DZ + DY], n111 = m0[DZ + DY + DX];
     const bool zin = !g.walls || z + 1 < g.nz;  // the upper corners lie in the slit
     R m[8];
     m[0] = n000;
@@ -293,20 +341,106 @@ __global__ __launch_bounds__(256) void k_gamma(Geom g, Pad p, const R *__restric
     m[5] = ((n000 + n100) + (n001 + n101)) * R(0.25);
     m[6] = ((n000 + n010) + (n001 + n011)) * R(0.25);
     m[7] = (((n000 + n100) + (n010 + n110)) + ((n001 + n101) + (n011 + n111))) * R(0.125);
+    R val[8];
+    bool bad = false;
 #pragma unroll
     for (int hi = 0; hi < 8; ++hi) {
         const R eta = eta_per_n * m[hi];
-        R val;
         if (eta < R(1)) {
             const R om = R(1) - eta;
-            val = wS * (R(1) - R(0.5) * eta) / (om * om * om);
+            val[hi] = wS * (R(1) - R(0.5) * eta) / (om * om * om);
         } else {
-            if (hi < 4 || zin) raise_flag(flag, FLAG_ETA);
-            val = R(0);
+            bad = bad || hi < 4 || zin;
+            val[hi] = R(0);
         }
-        R *dst = gam_p + (long long)hi * p.NP;
-        for_images(g, p, x, y, z, [&](int k) { dst[k] = val; });
     }
+    if (bad) raise_flag(flag, FLAG_ETA);
+    for_images(g, p, x, y, z, [&](int k) {
+#pragma unroll
+        for (int hi = 0; hi < 8; ++hi) gam_p[(long long)hi * p.NP + k] = val[hi];
+    });
+}
+
+// generic: the ball from its table of window offsets (relative to the
+// corner of a node's ball window; order z, then y, then x), summed into 8
+// interleaved partial sums, point k into sum k mod 8 (the order of the
+// specialised kernel, so both give the same bits)
+template <typename R, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, const R *__restrict__ rho_p,
+                                                        const int *__restrict__ boff, int nball, R inv_nball,
+                                                        R eta_per_n, R wS, int tiles_x, int tiles_y, int tiles_z,
+                                                        R *__restrict__ gam_p, int *flag)
+{
+    constexpr int NT = TX * TY * TZ;
+    constexpr int MX = TX + 1, MY = TY + 1, MZ = TZ + 1, MN = MX * MY * MZ;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int LX = TX + 2 * rb + 1, LY = TY + 2 * rb + 1, LZ = TZ + 2 * rb + 1, LXY = LX * LY;
+    R *win = reinterpret_cast<R *>(lds_raw);
+    R *nb = win + (size_t)LX * LY * LZ;
+    density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
+    __syncthreads();
+    for (int e = threadIdx.x; e < MN; e += NT) {
+        const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
+        const int zz = tc.z0 + mz;
+        R v = 0;
+        if (!g.walls || (zz >= 0 && zz < g.nz)) {
+            const R *c = win + mz * LXY + my * LX + mx;
+            R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int k = 0;
+            for (; k + 8 <= nball; k += 8) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) s[m] += c[boff[k + m]];
+            }
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+                if (k + m < nball) s[m] += c[boff[k + m]];
+            v = (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))) * inv_nball;
+        }
+        nb[e] = v;
+    }
+    __syncthreads();
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    density_gamma<R, TX, TY>(g, p, x, y, z, nb + (tc.lz * MY + tc.ly) * MX + tc.lx, eta_per_n, wS, gam_p, flag);
+}
+
+// specialised for the ball of 2 sigma = S2: offsets are LDS immediates, the
+// sum runs in 8 interleaved partial sums
+template <typename R, int S2, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R *__restrict__ rho_p, R inv_nball,
+                                                          R eta_per_n, R wS, int tiles_x, int tiles_y, int tiles_z,
+                                                          R *__restrict__ gam_p, int *flag)
+{
+    using B = Ball<S2>;
+    constexpr int rb = B::RB, NT = TX * TY * TZ;
+    constexpr int MX = TX + 1, MY = TY + 1, MZ = TZ + 1, MN = MX * MY * MZ;
+    constexpr int LX = TX + 2 * rb + 1, LY = TY + 2 * rb + 1, LZ = TZ + 2 * rb + 1, LXY = LX * LY;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    R *win = reinterpret_cast<R *>(lds_raw);
+    R *nb = win + (size_t)LX * LY * LZ;
+    density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
+    __syncthreads();
+    for (int e = threadIdx.x; e < MN; e += NT) {
+        const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
+        const int zz = tc.z0 + mz;
+        R v = 0;
+        if (!g.walls || (zz >= 0 && zz < g.nz)) {
+            const R *c = win + mz * LXY + my * LX + mx;  // corner of the lane's ball window
+            R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            static_for<0, B::NB>([&](auto ki) __attribute__((always_inline)) {
+                constexpr int k = decltype(ki)::value;
+                s[k & 7] += c[(B::T.z[k] + rb) * LXY + (B::T.y[k] + rb) * LX + (B::T.x[k] + rb)];
+            });
+            v = (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))) * inv_nball;
+        }
+        nb[e] = v;
+    }
+    __syncthreads();
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    density_gamma<R, TX, TY>(g, p, x, y, z, nb + (tc.lz * MY + tc.ly) * MX + tc.lx, eta_per_n, wS, gam_p, flag);
 }
 
 // uniform offsets of the four members (+-a, +-b, c) of a quad: source node
@@ -339,31 +473,6 @@ __device__ __forceinline__ void quad_offsets(int a, int b, int c, int PX, int PX
 // whose rings do not fit in LDS).  Blocks are ordered so that each XCD gets
 // a contiguous run of tiles (shared halos stay in that XCD's L2).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_tile(int id, int nb)
-{
-    const int xcd = id & 7, qq = nb >> 3, rem = nb & 7;
-    return (xcd < rem ? xcd * (qq + 1) : rem * (qq + 1) + (xcd - rem) * qq) + (id >> 3);
-}
-
-struct TileCoord {
-    int x0, y0, z0, lx, ly, lz;
-};
-
-template <int TX, int TY, int TZ>
-__device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int tiles_z)
-{
-    TileCoord t;
-    const int lid = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
-    const int t1 = lid / tiles_x;
-    t.x0 = (lid % tiles_x) * TX;
-    t.y0 = (t1 % tiles_y) * TY;
-    t.z0 = (t1 / tiles_y) * TZ;
-    t.lx = threadIdx.x % TX;
-    t.ly = (threadIdx.x / TX) % TY;
-    t.lz = threadIdx.x / (TX * TY);
-    return t;
-}
-
 // the gamma ring of one block: element e of a slice is sub-lattice
 // e / LG, row (e % LG) / LXg, column (e % LG) % LXg of the window whose
 // origin is the tile origin shifted by floor(-R/2) in x and y
@@ -799,24 +908,6 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
 // every LDS offset is an immediate and every weight a literal.  Offsets are
 // taken from the corner of each lane's stencil window (non-negative).
 // ---------------------------------------------------------------------------
-// The sums of a c-step are finished before its barrier: an empty asm that
-// reads and writes the accumulator keeps the compiler from sinking the
-// arithmetic of every c-step to the end of the kernel (which would keep all
-// loaded operands of the whole shell live at once).  It emits no code.
-__device__ __forceinline__ void pin(float &v) { asm volatile("" : "+v"(v)); }
-__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
-
-template <int B, typename F, int... I>
-__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
-{
-    (f(std::integral_constant<int, B + I>{}), ...);
-}
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (E > B) static_for_seq<B>(f, std::make_integer_sequence<int, E - B>{});
-}
-
 template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
 __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const R *__restrict__ rho_p,
                                                             const R *__restrict__ jx, const R *__restrict__ jy,
@@ -933,8 +1024,19 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const long long N = g.N;
-    D rho, jx, jy, jz;
-    pull_moments<R, HS>(g, ru_in, h_in, x, y, z, rho, jx, jy, jz);
+    const int r = (z * g.ny + y) * g.nx + x;
+    // the 19 pulled populations, kept for the collision (moments summed in
+    // the order of pull_moments)
+    D f[Q];
+    D rho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        f[a] = fpull<R, HS>(g, ru_in, h_in, x, y, z, r, a);
+        rho += f[a];
+        if (CX[a]) jx += D(CX[a]) * f[a];
+        if (CY[a]) jy += D(CY[a]) * f[a];
+        if (CZ[a]) jz += D(CZ[a]) * f[a];
+    }
     const D inv = D(1) / rho;
     const D Fx = Fi[i], Fy = Fi[N + i], Fz = Fi[2 * N + i];
     const D ux = (jx + D(0.5) * Fx) * inv, uy = (jy + D(0.5) * Fy) * inv, uz = (jz + D(0.5) * Fz) * inv;
@@ -952,13 +1054,12 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     const D dx = D(0.5) * Fx * inv, dy = D(0.5) * Fy * inv, dz = D(0.5) * Fz * inv;  // u* - u
     const D sx = D(2) * ux + dx, sy = D(2) * uy + dy, sz = D(2) * uz + dz;          // u + u*
     const D dsum = dx * sx + dy * sy + dz * sz;
-    const int r = (z * g.ny + y) * g.nx + x;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         const D w = wgt<D>(a);
         const D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
         const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * uu;
-        const D fneq = fpull<R, HS>(g, ru_in, h_in, x, y, z, r, a) - w * rho * (D(1) + P);
+        const D fneq = f[a] - w * rho * (D(1) + P);
         const D cF = D(CX[a]) * Fx + D(CY[a]) * Fy + D(CZ[a]) * Fz;
         const D guo = w * (D(3) * (cF - uF) + D(9) * cu * cF);
         const D cAc = D(CX[a] * CX[a]) * Axx + D(CY[a] * CY[a]) * Ayy + D(CZ[a] * CZ[a]) * Azz +

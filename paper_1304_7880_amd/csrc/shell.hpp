@@ -123,4 +123,54 @@ struct Shell {
     static constexpr int NQ = ShellTable<S2>::NQ;
 };
 
+// The ball of the smoothed density (Sec. 3): offsets with |e|^2 <= sigma^2/4
+// (16 |e|^2 <= s2^2), each weighted 1/|B|, in the order z, then y, then x.
+constexpr int ball_reach2(int s2)
+{
+    int r = 0;
+    const int L = shell_lim2(s2);
+    for (int z = -L; z <= L; ++z)
+        for (int y = -L; y <= L; ++y)
+            for (int x = -L; x <= L; ++x)
+                if (16 * (x * x + y * y + z * z) <= s2 * s2 && (x < 0 ? -x : x) > r) r = x < 0 ? -x : x;
+    return r;
+}
+
+constexpr int ball_size2(int s2)
+{
+    int n = 0;
+    const int L = shell_lim2(s2);
+    for (int z = -L; z <= L; ++z)
+        for (int y = -L; y <= L; ++y)
+            for (int x = -L; x <= L; ++x) n += 16 * (x * x + y * y + z * z) <= s2 * s2 ? 1 : 0;
+    return n;
+}
+
+template <int S2>
+struct BallTable {
+    static constexpr int RB = ball_reach2(S2);
+    static constexpr int NB = ball_size2(S2);
+    int x[NB], y[NB], z[NB];
+    constexpr BallTable() : x{}, y{}, z{}
+    {
+        int n = 0;
+        for (int k = -RB; k <= RB; ++k)
+            for (int j = -RB; j <= RB; ++j)
+                for (int i = -RB; i <= RB; ++i)
+                    if (16 * (i * i + j * j + k * k) <= S2 * S2) {
+                        x[n] = i;
+                        y[n] = j;
+                        z[n] = k;
+                        ++n;
+                    }
+    }
+};
+
+template <int S2>
+struct Ball {
+    static constexpr BallTable<S2> T{};
+    static constexpr int RB = BallTable<S2>::RB;
+    static constexpr int NB = BallTable<S2>::NB;
+};
+
 }  // namespace wdlb

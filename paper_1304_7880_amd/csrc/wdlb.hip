@@ -39,7 +39,7 @@ struct wdlb_ctx {
     size_t ws_bytes;
     // carved device arrays
     void *ru[2], *h[2];                  // state: (rho, u*) and deviations, two parities
-    void *rho_p, *nbar_p, *gam_p, *ru1_p;  // padded per-step arrays
+    void *rho_p, *gam_p, *ru1_p;  // padded per-step arrays
     void *jx, *jy, *jz, *fmf, *F, *A, *u_rd, *rho_rd;
     void *scratch;                        // >= 8 N reals, free between steps
     size_t padded_bytes;                  // bytes from rho_p to the end of ru1_p
@@ -48,11 +48,13 @@ struct wdlb_ctx {
     void *quads;
     int *qstart;
     int *ball;
-    int nq, nball, reach;
+    int nq, nball, rb, reach;  // quad count; ball size and reach; shell reach
+    int dtile;                 // k_density tile (index into DENSITY_TILES)
     double wS;         // 4 pi / |S|
     int tile;          // contact-shell tile variant (index into SHELL_TILES)
     int tile_req;      // requested variant, -1 = automatic
     int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
+    int spec_b2;       // 2 sigma of the specialised density kernel in use, 0 = generic
     int cur;
     int64_t step;
     bool inited;
@@ -135,7 +137,7 @@ Pad make_pad(const wdlb_lattice_desc *d, int P)
 }
 
 struct Layout {
-    size_t off_ru[2], off_h[2], off_rho_p, off_nbar_p, off_gam_p, off_ru1_p, off_j[3], off_fmf, off_F, off_A, off_urd,
+    size_t off_ru[2], off_h[2], off_rho_p, off_gam_p, off_ru1_p, off_j[3], off_fmf, off_F, off_A, off_urd,
         off_rhord, off_planes, off_flag, off_quads, off_qstart, off_ball, total;
 };
 
@@ -160,7 +162,6 @@ Layout layout(const wdlb_lattice_desc *d)
         L.off_h[b] = take(19 * hs * N);
     }
     L.off_rho_p = take(r * NP);
-    L.off_nbar_p = take(r * NP);
     L.off_gam_p = take(8 * r * NP);
     L.off_ru1_p = take(4 * r * NP);
     for (int c = 0; c < 3; ++c) L.off_j[c] = take(r * N);
@@ -231,6 +232,22 @@ constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
 static_assert(NTILES == WDLB_NTILES, "the header's variant count");
 constexpr size_t LDS_MAX = 160 * 1024;
 
+// k_density tiles: 32 x 8 x 2 while its LDS stays within 64 KB (several
+// blocks per CU), else 16 x 8 x 1
+struct DensityTile {
+    int TX, TY, TZ;
+    size_t lds_cap;
+};
+constexpr DensityTile DENSITY_TILES[2] = {{32, 8, 2, 64 * 1024}, {16, 8, 1, 160 * 1024}};
+constexpr bool density_fits(const DensityTile &t, int rb, size_t rbytes)
+{
+    return density_lds_bytes(t.TX, t.TY, t.TZ, rb, rbytes) <= t.lds_cap;
+}
+constexpr int pick_density_tile(int rb, size_t rbytes)
+{
+    return density_fits(DENSITY_TILES[0], rb, rbytes) ? 0 : (density_fits(DENSITY_TILES[1], rb, rbytes) ? 1 : -1);
+}
+
 constexpr bool tile_fits(const ShellTile &t, int reach, size_t rbytes)
 {
     const int NT = t.TX * t.TY * t.TZ;
@@ -268,15 +285,33 @@ wdlb_status upload_tables(wdlb_ctx *c)
     std::vector<int> qs(2 * reach + 2, 0);
     for (auto &e : q) qs[e.c + reach + 1]++;
     for (int k = 1; k < (int)qs.size(); ++k) qs[k] += qs[k - 1];
-    std::vector<int> b;
-    int RB = (int)std::ceil(c->prm.sigma / 2.0) + 1;
+    // the ball |e|^2 <= sigma^2/4 (order z, then y, then x), its reach and
+    // the density tile
+    std::vector<int> bx, by, bz;
+    int rb = 0;
+    const double s2 = c->prm.sigma * c->prm.sigma;
+    const int RB = (int)std::ceil(c->prm.sigma / 2.0) + 1;
     for (int z = -RB; z <= RB; ++z)
         for (int y = -RB; y <= RB; ++y)
             for (int x = -RB; x <= RB; ++x)
-                if (4.0 * (x * x + y * y + z * z) <= c->prm.sigma * c->prm.sigma)
-                    b.push_back(x + y * c->pad.PX + z * c->pad.PXY);
-    if ((int)b.size() > MAX_BALL) return fail(c, WDLB_E_INVAL, "stencil too large");
+                if (4.0 * (x * x + y * y + z * z) <= s2) {
+                    bx.push_back(x);
+                    by.push_back(y);
+                    bz.push_back(z);
+                    rb = std::max(rb, std::abs(x));
+                }
+    if ((int)bx.size() > MAX_BALL) return fail(c, WDLB_E_INVAL, "stencil too large");
+    if (rb + 1 > c->pad.P) return fail(c, WDLB_E_INVAL, "sigma too small for the padded arrays");
+    int dtile = -1;
+    for (int k = 0; k < 2 && dtile < 0; ++k)
+        if (density_fits(DENSITY_TILES[k], rb, sizeof(R))) dtile = k;
+    if (dtile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the density tiles");
+    // window offsets of the ball from the corner of a node's window
+    const int LX = DENSITY_TILES[dtile].TX + 2 * rb + 1, LY = DENSITY_TILES[dtile].TY + 2 * rb + 1;
+    std::vector<int> b(bx.size());
+    for (size_t k = 0; k < bx.size(); ++k) b[k] = (bz[k] + rb) * LX * LY + (by[k] + rb) * LX + (bx[k] + rb);
     c->spec_s2 = 0;
+    c->spec_b2 = c->tile_req >= 0 ? 0 : specialised_s2(c->prm.sigma);
     if (c->tile_req >= 0) {
         if (!tile_fits(SHELL_TILES[c->tile_req], reach, sizeof(R)))
             return fail(c, WDLB_E_INVAL, "the requested shell tile does not fit this sigma");
@@ -294,6 +329,8 @@ wdlb_status upload_tables(wdlb_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->nq = (int)q.size();
     c->nball = (int)b.size();
+    c->rb = rb;
+    c->dtile = dtile;
     c->reach = reach;
     c->wS = 4.0 * M_PI / nshell;
     return WDLB_OK;
@@ -307,8 +344,8 @@ wdlb_status tables(wdlb_ctx *c)
 
 inline dim3 grid1(long long N, int bs) { return dim3((unsigned)((N + bs - 1) / bs)); }
 
-enum { K_MOMENTS = 0, K_BALL, K_GAMMA, K_MEANFIELD, K_SHELL, K_COLLIDE };
-const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_ball", "k_gamma", "k_meanfield", "k_shell", "k_collide"};
+enum { K_MOMENTS = 0, K_DENSITY, K_MEANFIELD, K_SHELL, K_COLLIDE };
+const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide"};
 
 hipEvent_t take_event(wdlb_ctx *c)
 {
@@ -449,6 +486,60 @@ wdlb_status launch_shells(wdlb_ctx *c)
     }
 }
 
+template <typename R, int TX, int TY, int TZ>
+wdlb_status launch_density_g(wdlb_ctx *c)
+{
+    const Geom g = c->g;
+    const double s = c->prm.sigma;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const size_t lds = density_lds_bytes(TX, TY, TZ, c->rb, sizeof(R));
+    auto kern = k_density<R, TX, TY, TZ>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return launch(c, K_DENSITY, [&] {
+        hipLaunchKernelGGL(kern, dim3(tx * ty * tz), dim3(TX * TY * TZ), lds, c->stream, g, c->pad, c->rb,
+                           (const R *)c->rho_p, (const int *)c->ball, c->nball, R(1.0 / c->nball),
+                           R(M_PI * s * s * s / 6.0), R(c->wS), tx, ty, tz, (R *)c->gam_p, c->flag);
+    });
+}
+
+// specialised for the ball of 2 sigma = S2 on the tile the automatic choice
+// takes for it
+template <typename R, int S2>
+wdlb_status launch_density_s(wdlb_ctx *c)
+{
+    constexpr int RB = Ball<S2>::RB;
+    constexpr int DT = pick_density_tile(RB, sizeof(R));
+    static_assert(DT >= 0, "no density tile for this ball");
+    constexpr int TX = DENSITY_TILES[DT].TX, TY = DENSITY_TILES[DT].TY, TZ = DENSITY_TILES[DT].TZ;
+    if (c->rb != RB || c->nball != Ball<S2>::NB || c->dtile != DT)
+        return fail(c, WDLB_E_STATE, "compiled ball does not match the ball of sigma");
+    const Geom g = c->g;
+    const double s = c->prm.sigma;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const size_t lds = density_lds_bytes(TX, TY, TZ, RB, sizeof(R));
+    auto kern = k_density_s<R, S2, TX, TY, TZ>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return launch(c, K_DENSITY, [&] {
+        hipLaunchKernelGGL(kern, dim3(tx * ty * tz), dim3(TX * TY * TZ), lds, c->stream, g, c->pad,
+                           (const R *)c->rho_p, R(1.0 / c->nball), R(M_PI * s * s * s / 6.0), R(c->wS), tx, ty, tz,
+                           (R *)c->gam_p, c->flag);
+    });
+}
+
+template <typename R>
+wdlb_status launch_density(wdlb_ctx *c)
+{
+    switch (c->spec_b2) {
+    case 6: return launch_density_s<R, 6>(c);
+    case 8: return launch_density_s<R, 8>(c);
+    case 12: return launch_density_s<R, 12>(c);
+    case 16: return launch_density_s<R, 16>(c);
+    case 20: return launch_density_s<R, 20>(c);
+    default: break;
+    }
+    return c->dtile == 0 ? launch_density_g<R, 32, 8, 2>(c) : launch_density_g<R, 16, 8, 1>(c);
+}
+
 // one pass of the step kernels on the current buffers; READ stops after the
 // fields (u = (j + F/2)/rho into u_rd) and leaves the state untouched
 template <typename R, typename HS, bool READ>
@@ -470,15 +561,7 @@ wdlb_status run_pass(wdlb_ctx *c)
     });
     if (st != WDLB_OK) return st;
     if (p.nonlocal) {
-        st = launch(c, K_BALL, [&] {
-            hipLaunchKernelGGL((k_ball<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->rho_p,
-                               (const int *)c->ball, c->nball, R(1.0 / c->nball), (R *)c->nbar_p);
-        });
-        if (st != WDLB_OK) return st;
-        st = launch(c, K_GAMMA, [&] {
-            hipLaunchKernelGGL((k_gamma<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->nbar_p,
-                               R(M_PI * s * s * s / 6.0), R(c->wS), (R *)c->gam_p, c->flag);
-        });
+        st = launch_density<R>(c);
         if (st != WDLB_OK) return st;
         st = launch_shells<R>(c);
         if (st != WDLB_OK) return st;
@@ -605,7 +688,6 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
         c->h[b] = c->ws + L.off_h[b];
     }
     c->rho_p = c->ws + L.off_rho_p;
-    c->nbar_p = c->ws + L.off_nbar_p;
     c->gam_p = c->ws + L.off_gam_p;
     c->ru1_p = c->ws + L.off_ru1_p;
     c->padded_bytes = L.off_j[0] - L.off_rho_p;
@@ -954,7 +1036,7 @@ void wdlb_destroy(wdlb_ctx *c)
 {
     if (!c) return;
     prof_flush(c);
-    for (auto e : c->ev_free) hipEventDestroy(e);
+    for (auto e : c->ev_free) (void)hipEventDestroy(e);
     delete c;
 }
 
