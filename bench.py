@@ -7,13 +7,14 @@ tau = 0.8, g_x = 1e-6 and a seeded +-1 % density noise, FP32 populations
 (the configuration on which the throughput metric is quoted).  Inputs are
 synthetic and resident on the device before the timed region starts.
 
-A step is one full WDLB step: moments, weighted density, contact values,
-mean-field shell sum, viscous/SMDB shell sum with the forced collision, and
+A step is one full WDLB step: moments, weighted density and contact values,
+mean-field shell sum, viscous/SMDB shell sum, and the forced collision with
 the stream.  value = fluid nodes x steps / device time of the timed steps
-(MLUPS).  The dominant kernel (k_shell) is timed with HIP events on the
-library's stream during the same run and priced against the chip's FP32
-vector peak; the FP64 CPU oracle is timed on a bounded sample on the host.
-Prints one JSON line.
+(MLUPS).  The dominant kernel (the viscous/SMDB shell sum) is timed with HIP
+events on the library's stream during the same run and priced against the
+chip's FP32 vector peak; HBM bytes per launch come from the rocprofv3
+counter summary in profiles/ while it matches the device sources.  The FP64
+CPU oracle is timed on a bounded sample on the host.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -53,19 +54,28 @@ def device_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+PROFILE = os.path.join(ROOT, "profiles", "step_kernels_slab64.md")
+
+
 def measured_traffic():
-    """Calibrated HBM bytes per k_shell launch from the rocprofv3 counter runs
-    summarised in profiles/, or None if the device code changed since."""
-    path = os.path.join(ROOT, "profiles", "k_shell_slab64.md")
-    if not os.path.exists(path):
+    """Calibrated HBM bytes per launch of each step kernel, from the rocprofv3
+    counter runs summarised in PROFILE, or None if the device code changed
+    since they were taken."""
+    if not os.path.exists(PROFILE):
         return None
-    kv = {}
-    for line in open(path):
-        if ":" in line and line.split(":")[0].strip() in ("k_shell_traffic_bytes_per_launch", "device_source_sha256_16"):
-            kv[line.split(":")[0].strip()] = line.split(":", 1)[1].strip()
-    if kv.get("device_source_sha256_16") != device_source_hash():
+    kv, traffic = {}, {}
+    for line in open(PROFILE):
+        if ":" not in line:
+            continue
+        key, val = line.split(":", 1)
+        key, val = key.strip(), val.strip()
+        if key == "device_source_sha256_16":
+            kv[key] = val
+        elif key.startswith("traffic_bytes_per_launch "):
+            traffic[key.split()[1]] = float(val)
+    if kv.get("device_source_sha256_16") != device_source_hash() or not traffic:
         return None
-    return float(kv["k_shell_traffic_bytes_per_launch"])
+    return traffic
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -125,8 +135,10 @@ def main():
     ctx.step(args.warmup)
     ctx.sync()
 
-    # timed region: K steps bracketed by synchronisations; events on the library's stream
-    ctx.profile(True)
+    # timed region: K steps bracketed by synchronisations; HIP events on the
+    # library's stream around every launch of the dominant kernel
+    shell_name = "k_shell_s" if ctx.get_tile()[1] else "k_shell"
+    ctx.profile(True, kernels=["k_shell"])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,16 +149,25 @@ def main():
     wall = time.perf_counter() - t0
     ctx.sync()
     dev_ms = e0.elapsed_time(e1)
+    k_ms, k_n = ctx.profile_read()["k_shell"]
+    ctx.profile(False)
+
+    # per-kernel breakdown (events around every launch), after the timed region
+    nb = min(args.steps, 200)
+    ctx.profile(True)
+    ctx.step(nb)
     kstats = ctx.profile_read()
     ctx.profile(False)
 
     ms_per_step = dev_ms / args.steps
     mlups = w.N * args.steps / (dev_ms * 1e-3) / 1e6
-    k_ms, k_n = kstats["k_shell"]
     k_avg_s = k_ms * 1e-3 / k_n
     flops = shell_flops_per_node(w.sigma) * w.N
     achieved = flops / k_avg_s / 1e12
     J, upore, mass = ctx.read_flux()
+    traffic = measured_traffic()
+    shell_traffic = traffic.get(shell_name) if traffic else None
+    step_bytes = sum(traffic.values()) if traffic else None
 
     out = {
         "metric": "MLUPS (incl. nonlocal force)",
@@ -163,11 +184,15 @@ def main():
         "data": "synthetic (seeded +-1% density noise, uniform start)",
         "config": {"workload": w.name, "nodes": w.N, "sigma": w.sigma, "eta": w.eta, "tau": w.tau,
                    "precision": "fp32 populations (f - feq encoding), fp64 reductions"},
-        "roofline": {"bound": "alu", "kernel": "k_shell", "achieved": round(achieved, 3),
+        "roofline": {"bound": "alu", "kernel": shell_name, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": shell_traffic,
                      "avg_kernel_ms": round(k_avg_s * 1e3, 5),
                      "flops_per_launch": flops},
+        "step_hbm": None if step_bytes is None else {
+            "bytes_per_step": step_bytes, "achieved_GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+            "peak_GBs": PEAK_HBM_GBS,
+            "frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in kstats.items()},
         "wall_s": round(wall, 4),
         "pore_flux": J,

@@ -147,14 +147,16 @@ wdlb_status wdlb_load_state(wdlb_ctx *ctx, const void *h_buf, size_t bytes);
 wdlb_status wdlb_get_step(const wdlb_ctx *ctx, int64_t *step);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every kernel launch of wdlb_step (off by default; a few microseconds of
- * event overhead per launch when on).  wdlb_profile(ctx, 1) enables and
- * resets the totals, wdlb_profile(ctx, 0) disables.  wdlb_profile_read
- * synchronises and returns, for kernel id k (0 .. WDLB_NKERNELS-1), the
- * summed device time in milliseconds and the number of launches timed.
- * wdlb_kernel_name(k) names the kernel ("" for an unknown id). */
+ * the kernel launches of wdlb_step (off by default; each timed launch costs
+ * a few microseconds of event overhead).  wdlb_profile(ctx, mask) times the
+ * kernels whose id k has bit k set in mask (-1: all) and resets the totals;
+ * mask 0 disables.  wdlb_profile_read synchronises and returns, for kernel
+ * id k (0 .. WDLB_NKERNELS-1), the summed device time in milliseconds and
+ * the number of launches timed.  wdlb_kernel_name(k) names the kernel (""
+ * for an unknown id): 0 moments, 1 density, 2 meanfield, 3 shell,
+ * 4 collide. */
 #define WDLB_NKERNELS 5
-wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t enable);
+wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t mask);
 wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 const char *wdlb_kernel_name(int32_t kernel);
 

@@ -60,7 +60,7 @@ struct wdlb_ctx {
     bool inited;
     std::string err;
     // event timing of the step kernels
-    bool prof = false;
+    int prof = 0;  // bit k: time kernel k
     std::vector<hipEvent_t> ev_free;
     struct Pending {
         int k;
@@ -380,7 +380,7 @@ wdlb_status prof_flush(wdlb_ctx *c)
 template <typename L>
 wdlb_status launch(wdlb_ctx *c, int k, L &&fn)
 {
-    if (!c->prof) {
+    if (!(c->prof >> k & 1)) {
         fn();
         return WDLB_OK;
     }
@@ -624,8 +624,8 @@ wdlb_status copy_out_r(wdlb_ctx *c, const void *dev, size_t n, double *host)
 wdlb_status read_pass(wdlb_ctx *c)
 {
     if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
-    bool prof = c->prof;
-    c->prof = false;  // only the stepping kernels are timed
+    const int prof = c->prof;
+    c->prof = 0;  // only the stepping kernels are timed
     wdlb_status st = pass<true>(c);
     c->prof = prof;
     if (st != WDLB_OK) return st;
@@ -981,17 +981,17 @@ wdlb_status wdlb_get_step(const wdlb_ctx *c, int64_t *step)
     return WDLB_OK;
 }
 
-wdlb_status wdlb_profile(wdlb_ctx *c, int32_t enable)
+wdlb_status wdlb_profile(wdlb_ctx *c, int32_t mask)
 {
     if (!c) return WDLB_E_INVAL;
     wdlb_status st = prof_flush(c);
     if (st != WDLB_OK) return st;
-    if (enable)
+    if (mask)
         for (int k = 0; k < WDLB_NKERNELS; ++k) {
             c->prof_ms[k] = 0;
             c->prof_n[k] = 0;
         }
-    c->prof = enable != 0;
+    c->prof = mask & ((1 << WDLB_NKERNELS) - 1);
     return WDLB_OK;
 }
 

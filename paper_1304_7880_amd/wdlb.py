@@ -221,8 +221,18 @@ class Context:
         buf = C.create_string_buffer(data, len(data))
         self._chk(self._L.wdlb_load_state(self.h, buf, len(data)), "load_state")
 
-    def profile(self, enable=True):
-        self._chk(self._L.wdlb_profile(self.h, int(bool(enable))), "profile")
+    def profile(self, enable=True, kernels=None):
+        """Time the step kernels with HIP events: all of them, or only those
+        named in kernels; enable=False stops."""
+        mask = 0
+        if enable:
+            if kernels is None:
+                mask = -1
+            else:
+                names = [self._L.wdlb_kernel_name(k).decode() for k in range(NKERNELS)]
+                for n in kernels:
+                    mask |= 1 << names.index(n)
+        self._chk(self._L.wdlb_profile(self.h, mask), "profile")
 
     def profile_read(self):
         """{kernel name: (total ms, launches)} of the timed step kernels (synchronises)."""
