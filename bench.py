@@ -28,7 +28,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, 256 CU x 2.4 GHz (dual-issue FP32); 78.6 without packed FP32
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CU x 4 SIMD x 64 flop/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -46,11 +46,15 @@ def shell_flops_per_node(sigma: float) -> float:
 
 
 def device_source_hash() -> str:
-    """sha256 (16 hex) of the device sources, to tie counter data to them."""
+    """sha256 (16 hex) of the device sources with comments and blank space
+    removed, to tie counter data to the code they were taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("d3q19.hpp", "shell.hpp", "kernels.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1304_7880_amd", "csrc", name), "rb").read())
+        src = open(os.path.join(ROOT, "paper_1304_7880_amd", "csrc", name)).read()
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -151,9 +151,9 @@ __device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int ti
 // mass) next to a tiny flow part, and FP32 products c.u* and sums of
 // populations of size w rho lose the flow to rounding.  FP64 sums of the
 // stored parts are exact enough that no special summation order is needed.
-// On gfx950 an FP64 FMA issues at the rate of an unpacked FP32 FMA, and this
-// part is a few percent of the step's arithmetic; storage keeps the
-// precision of the mode.
+// On gfx950 an FP64 FMA issues at half the FP32 rate, and this part is a
+// few percent of the step's arithmetic; storage keeps the precision of the
+// mode.
 // ---------------------------------------------------------------------------
 typedef double D;
 
