@@ -46,10 +46,16 @@ struct bf16 {
     uint16_t bits;
 };
 
-template <typename R>
-__device__ __forceinline__ R load_h(const R *p) { return *p; }
-template <typename R>
-__device__ __forceinline__ void store_h(R *p, R v) { *p = v; }
+// BF16 mode: h carries no mass and no momentum, but its BF16 roundings do.
+// Four populations (rest, +x, +y, +z) are therefore stored in FP32 and set
+// from the rounded others so that the stored h closes mass and momentum:
+// the FP32 value is split into its high half (in the population's own
+// plane) and its low half (in plane 19 + closure slot).
+__host__ __device__ constexpr int closure_slot(int a) { return a == 0 ? 0 : (a == 1 ? 1 : (a == 3 ? 2 : (a == 5 ? 3 : -1))); }
+template <typename HS>
+__host__ __device__ constexpr int hplanes() { return 19; }
+template <>
+__host__ __device__ constexpr int hplanes<bf16>() { return 23; }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f)
@@ -59,6 +65,29 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
     if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
     u += 0x7fffu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
+}
+
+// Stochastic rounding to BF16: the FP32 bit pattern of |v| plus a uniform
+// 16-bit integer, truncated to its upper half, is v rounded up or down with
+// probabilities given by the distance to the two neighbours (unbiased).
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16(f);
+    const uint32_t mag = u & 0x7fffffffu;
+    const uint32_t up = mag + (r16 & 0xffffu);
+    if ((up & 0x7f800000u) == 0x7f800000u) return f32_to_bf16(f);  // would round to infinity
+    return uint16_t(((u & 0x80000000u) | up) >> 16);
+}
+
+// SplitMix64 output function (Steele, Lea and Flood, 2014): a counter-based
+// source of 64 random bits per input
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
 }
 
 // P_a(u) for the velocity a (compile-time after unrolling)

@@ -29,6 +29,7 @@
 // differences of mirror images before they are accumulated, so a state that
 // does not depend on x or y gives exactly zero x and y forces.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "d3q19.hpp"
@@ -80,23 +81,41 @@ __device__ __forceinline__ void for_images(const Geom &g, const Pad &p, int x, i
     }
 }
 
+// h_a of node s (plane a of N); see closure_slot for the BF16 planes
 template <typename R, typename HS>
-__device__ __forceinline__ R ldh(const HS *p);
+__device__ __forceinline__ R ldh(const HS *h, int a, long long N, long long s)
+{
+    return h[a * N + s];
+}
 template <>
-__device__ __forceinline__ float ldh<float, float>(const float *p) { return *p; }
-template <>
-__device__ __forceinline__ double ldh<double, double>(const double *p) { return *p; }
-template <>
-__device__ __forceinline__ float ldh<float, bf16>(const bf16 *p) { return bf16_to_f32(p->bits); }
+__device__ __forceinline__ float ldh<float, bf16>(const bf16 *h, int a, long long N, long long s)
+{
+    const uint16_t hi = h[a * N + s].bits;
+    const int k = closure_slot(a);
+    if (k < 0) return bf16_to_f32(hi);
+    const uint16_t lo = h[(19 + k) * N + s].bits;
+    return __uint_as_float((uint32_t(hi) << 16) | uint32_t(lo));
+}
 
+// store h_a of node i: FP32/FP64 as is; BF16 rounded, except the closure
+// populations, which keep their FP32 value exactly
 template <typename R, typename HS>
-__device__ __forceinline__ void sth(HS *p, R v);
+__device__ __forceinline__ void sth(HS *h, int a, long long N, long long i, R v)
+{
+    h[a * N + i] = v;
+}
 template <>
-__device__ __forceinline__ void sth<float, float>(float *p, float v) { *p = v; }
-template <>
-__device__ __forceinline__ void sth<double, double>(double *p, double v) { *p = v; }
-template <>
-__device__ __forceinline__ void sth<float, bf16>(bf16 *p, float v) { p->bits = f32_to_bf16(v); }
+__device__ __forceinline__ void sth<float, bf16>(bf16 *h, int a, long long N, long long i, float v)
+{
+    const int k = closure_slot(a);
+    if (k < 0) {
+        h[a * N + i].bits = f32_to_bf16(v);
+    } else {
+        const uint32_t u = __float_as_uint(v);
+        h[a * N + i].bits = uint16_t(u >> 16);
+        h[(19 + k) * N + i].bits = uint16_t(u & 0xffffu);
+    }
+}
 
 __device__ __forceinline__ void raise_flag(int *flag, int bit)
 {
@@ -182,7 +201,7 @@ __device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, 
     D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
     if (bb) cu = -cu;
     const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * (ux * ux + uy * uy + uz * uz);
-    return wgt<D>(a) * D(q.x) * (D(1) + P) + D(ldh<R, HS>(h + (long long)ha * g.N + s));
+    return wgt<D>(a) * D(q.x) * (D(1) + P) + D(ldh<R, HS>(h, ha, g.N, s));
 }
 
 template <typename R, typename HS>
@@ -248,7 +267,7 @@ __global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ 
             D Pt = D(3) * ct + D(4.5) * ct * ct - D(1.5) * (ty_ * ty_ + tz_ * tz_ + tw * tw);
             val = w * ((D(t.x) - qx) + (D(t.x) * Pt - qx * Ps));
         }
-        sth<R, HS>(h + (long long)a * g.N + i, R(val));
+        sth<R, HS>(h, a, g.N, i, R(val));
     }
 }
 
@@ -1018,7 +1037,7 @@ template <typename R, typename HS, bool READ>
 __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ Fi, const R *__restrict__ Ai,
                                                  R omega, R ksrc, const V4<R> *__restrict__ ru_in,
                                                  const HS *__restrict__ h_in, V4<R> *__restrict__ ru_out,
-                                                 HS *__restrict__ h_out, R *__restrict__ u_rd)
+                                                 HS *__restrict__ h_out, R *__restrict__ u_rd, uint64_t step)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
@@ -1054,6 +1073,7 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     const D dx = D(0.5) * Fx * inv, dy = D(0.5) * Fy * inv, dz = D(0.5) * Fz * inv;  // u* - u
     const D sx = D(2) * ux + dx, sy = D(2) * uy + dy, sz = D(2) * uz + dz;          // u + u*
     const D dsum = dx * sx + dy * sy + dz * sz;
+    D hv[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         const D w = wgt<D>(a);
@@ -1068,7 +1088,38 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
         const D cd = D(CX[a]) * dx + D(CY[a]) * dy + D(CZ[a]) * dz;
         const D cs = D(CX[a]) * sx + D(CY[a]) * sy + D(CZ[a]) * sz;
         const D deq = w * rho * (-D(3) * cd - D(4.5) * cd * cs + D(1.5) * dsum);
-        sth<R, HS>(h_out + (long long)a * N + i, R(keep * fneq + deq + ks * (guo + sa)));
+        hv[a] = keep * fneq + deq + ks * (guo + sa);
+    }
+    if constexpr (std::is_same<HS, bf16>::value) {
+        // round the others stochastically (dither from a counter-based
+        // generator keyed by step, node and population), then close mass
+        // and momentum with the FP32 four
+        uint64_t rnd[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rnd[k] = splitmix64((step << 34) ^ ((uint64_t)i << 2) ^ (uint64_t)k);
+        D m = 0, mx = 0, my = 0, mz = 0;
+        int nb = 0;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if (closure_slot(a) >= 0) continue;
+            const uint32_t r16 = uint32_t(rnd[nb >> 2] >> (16 * (nb & 3))) & 0xffffu;
+            ++nb;
+            const uint16_t b = f32_to_bf16_sr(float(hv[a]), r16);
+            h_out[a * N + i].bits = b;
+            const D r = bf16_to_f32(b);
+            m += r;
+            if (CX[a]) mx += D(CX[a]) * r;
+            if (CY[a]) my += D(CY[a]) * r;
+            if (CZ[a]) mz += D(CZ[a]) * r;
+        }
+        const D h1 = -mx, h3 = -my, h5 = -mz;
+        sth<R, HS>(h_out, 1, N, i, R(h1));
+        sth<R, HS>(h_out, 3, N, i, R(h3));
+        sth<R, HS>(h_out, 5, N, i, R(h5));
+        sth<R, HS>(h_out, 0, N, i, R(-(m + h1 + h3 + h5)));
+    } else {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) sth<R, HS>(h_out, a, N, i, R(hv[a]));
     }
     ru_out[i] = V4<R>{R(rho), R(ux + dx), R(uy + dy), R(uz + dz)};
 }

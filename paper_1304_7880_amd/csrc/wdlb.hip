@@ -35,6 +35,7 @@ struct wdlb_ctx {
     int prec;
     size_t rsize;      // bytes of one real (compute type)
     size_t hsize;      // bytes of one stored h
+    int hplanes;       // planes of h per node (19; 23 in the BF16 mode)
     char *ws;
     size_t ws_bytes;
     // carved device arrays
@@ -159,7 +160,7 @@ Layout layout(const wdlb_lattice_desc *d)
     };
     for (int b = 0; b < 2; ++b) {
         L.off_ru[b] = take(4 * r * N);
-        L.off_h[b] = take(19 * hs * N);
+        L.off_h[b] = take((size_t)(d->precision == WDLB_BF16_NEQ ? hplanes<bf16>() : 19) * hs * N);
     }
     L.off_rho_p = take(r * NP);
     L.off_gam_p = take(8 * r * NP);
@@ -575,7 +576,7 @@ wdlb_status run_pass(wdlb_ctx *c)
     st = launch(c, K_COLLIDE, [&] {
         hipLaunchKernelGGL((k_collide<R, HS, READ>), grid, dim3(bs), 0, c->stream, g, (const R *)c->F,
                            (const R *)c->A, R(1.0 / p.tau), R(1.0 - 0.5 / p.tau), ru_in, h_in, (V4<R> *)c->ru[nxt],
-                           (HS *)c->h[nxt], (R *)c->u_rd);
+                           (HS *)c->h[nxt], (R *)c->u_rd, (uint64_t)c->step);
     });
     if (st != WDLB_OK) return st;
     if (READ)
@@ -641,7 +642,7 @@ struct StateHeader {
 size_t state_bytes(const wdlb_ctx *c)
 {
     const size_t N = (size_t)c->g.N;
-    return sizeof(StateHeader) + 4 * c->rsize * N + 19 * c->hsize * N;
+    return sizeof(StateHeader) + 4 * c->rsize * N + (size_t)c->hplanes * c->hsize * N;
 }
 
 }  // namespace
@@ -675,6 +676,7 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->prec = desc->precision;
     c->rsize = c->prec == WDLB_FP64 ? 8 : 4;
     c->hsize = c->prec == WDLB_FP64 ? 8 : (c->prec == WDLB_BF16_NEQ ? 2 : 4);
+    c->hplanes = c->prec == WDLB_BF16_NEQ ? hplanes<bf16>() : 19;
     c->g.nx = desc->nx;
     c->g.ny = desc->ny;
     c->g.nz = desc->nz;
@@ -946,7 +948,7 @@ wdlb_status wdlb_save_state(wdlb_ctx *c, void *h_buf, size_t bytes)
     memcpy(p, &hd, sizeof(hd));
     const size_t N = (size_t)c->g.N;
     HIPCHK(c, hipMemcpyAsync(p + sizeof(hd), c->ru[c->cur], 4 * c->rsize * N, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(p + sizeof(hd) + 4 * c->rsize * N, c->h[c->cur], 19 * c->hsize * N,
+    HIPCHK(c, hipMemcpyAsync(p + sizeof(hd) + 4 * c->rsize * N, c->h[c->cur], (size_t)c->hplanes * c->hsize * N,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return WDLB_OK;
@@ -965,7 +967,7 @@ wdlb_status wdlb_load_state(wdlb_ctx *c, const void *h_buf, size_t bytes)
     const size_t N = (size_t)c->g.N;
     c->cur = 0;
     HIPCHK(c, hipMemcpyAsync(c->ru[0], p + sizeof(hd), 4 * c->rsize * N, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->h[0], p + sizeof(hd) + 4 * c->rsize * N, 19 * c->hsize * N, hipMemcpyHostToDevice,
+    HIPCHK(c, hipMemcpyAsync(c->h[0], p + sizeof(hd) + 4 * c->rsize * N, (size_t)c->hplanes * c->hsize * N, hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -1,0 +1,55 @@
+"""Write the column-oracle fixtures used by the full-size GPU parity tests.
+
+    python tests/golden/make_column_refs.py
+
+Every stored value comes from oracle/column1d.py (the FP64 1-D z-column
+oracle, exact for states that do not depend on x and y; pinned against the
+3-D oracle by tests/test_oracle_pins.py).  Inputs come from the seeded
+workload module only.  The fixtures are small JSON files:
+
+  slab_large_sub_10000.json  64x64x256 slit, sigma=10, eta=0.40, tau=0.7,
+                             g_x=5e-7, uniform start, 10000 steps
+  bulk128_shear_eta025_1000.json
+                             128^3 periodic cube, sigma=8, eta=0.25, tau=1,
+                             u_x = 1e-4 sin(2 pi z/128), 1000 steps
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle.column1d import Column  # noqa: E402
+from paper_1304_7880_amd.workloads import BULK_128, SLAB_LARGE_SUB  # noqa: E402
+
+
+def run(w, steps):
+    col = Column(w.nz, sigma=w.sigma, tau=w.tau, g=w.g, walls=w.walls_z)
+    z = np.arange(w.nz, dtype=np.float64)
+    u = np.zeros((3, w.nz))
+    u[0] = w.shear_amp * np.sin(2.0 * math.pi * z / w.nz)
+    col.init(np.full(w.nz, w.n0), u)
+    col.step(steps)
+    rho, ux, J, upore, mass = col.reduce()
+    return {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "walls_z": w.walls_z, "sigma": w.sigma,
+            "eta": w.eta, "tau": w.tau, "g": list(w.g), "shear_amp": w.shear_amp, "steps": steps,
+            "n_z": rho.tolist(), "ux_z": ux.tolist(), "j_pore": J, "u_pore": upore,
+            "generated_by": "tests/golden/make_column_refs.py with oracle/column1d.py (FP64)"}
+
+
+def main():
+    cases = [("slab_large_sub_10000.json", SLAB_LARGE_SUB, 10000),
+             ("bulk128_shear_eta025_1000.json", BULK_128.with_(eta=0.25), 1000)]
+    for name, w, steps in cases:
+        out = run(w, steps)
+        with open(os.path.join(HERE, name), "w") as f:
+            json.dump(out, f, indent=0)
+        print(name, "J", out["j_pore"], flush=True)
+
+
+if __name__ == "__main__":
+    main()
