@@ -188,6 +188,79 @@ const char *wdlb_last_error(const wdlb_ctx *ctx);
 /* Release the context (host memory only; the workspace stays the caller's). */
 void wdlb_destroy(wdlb_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Serving: batched solves of slit pores over resident requests (a project
+ * addition on top of the paper's step).  A server owns one lattice of
+ * nx x ny x nz planes (desc; walls_z must be 1, precision WDLB_FP32) and a
+ * worker thread.  A request is a slit of height H (fluid planes) with its own
+ * packing fraction eta (uniform start n0 = 6 eta / (pi sigma^3), u = 0),
+ * body force g_x and relaxation time tau; sigma and the x,y extent are the
+ * server's.  Resident requests are stacked along z, each followed by R gap
+ * planes (R = the shell reach of sigma) that no stencil crosses, and are
+ * stepped together, one launch chain per step.  A request is admitted
+ * (arrival order, skipping those that do not fit yet) when a run of H + R
+ * free planes exists, and retired when its pore flux changed by less than
+ * tol (relative) over the last check_every steps, or after max_steps
+ * (status WDLB_E_NOT_CONVERGED).  Its planes are then reused.  A request's
+ * result does not depend on the other residents.
+ *
+ * The caller owns the device pool (size from wdlb_server_workspace_size,
+ * 256-byte aligned); it must outlive the server.  The server runs its GPU
+ * work on a stream of its own on the device current at create.
+ * submit, poll, drain and stats may be called from any thread. */
+typedef struct wdlb_server wdlb_server;
+
+typedef struct {
+    double sigma;        /* hard-sphere diameter of every request */
+    double tol;          /* steady-state test |J(t) - J(t - check_every)| <= tol |J(t)| */
+    int32_t check_every; /* steps between flux checks (and admissions) */
+    int32_t pad;
+    int64_t max_steps;   /* cap per request */
+} wdlb_server_params;
+
+typedef struct {
+    int32_t H;           /* fluid planes of the slit (walls at z = -1/2 and H - 1/2) */
+    int32_t pad;
+    double eta, gx, tau;
+} wdlb_request;
+
+/* state: 0 queued, 1 running, 2 finished.  Times are seconds since the
+ * server was created: submitted, admitted, finished. */
+typedef struct {
+    int32_t state;
+    int32_t status;      /* wdlb_status of a finished request */
+    int32_t H;
+    int32_t pad;
+    int64_t steps;       /* steps taken */
+    double j_pore, u_pore;
+    double t_submit, t_admit, t_done;
+} wdlb_result;
+
+typedef struct {
+    int64_t chunks;        /* launch chains of check_every steps */
+    int64_t steps;         /* steps of the server lattice */
+    double node_updates;   /* fluid-node updates summed over steps */
+    int32_t resident, max_resident, queued, finished;
+    double busy_s;         /* wall time spent stepping */
+} wdlb_server_stats;
+
+wdlb_status wdlb_server_workspace_size(const wdlb_lattice_desc *desc, const wdlb_server_params *sp, size_t *bytes);
+wdlb_status wdlb_server_create(const wdlb_lattice_desc *desc, const wdlb_server_params *sp, void *d_pool,
+                               size_t bytes, wdlb_server **out);
+/* Queue a request; *id identifies it.  WDLB_E_INVAL if it can never fit or
+ * its parameters are invalid. */
+wdlb_status wdlb_server_submit(wdlb_server *srv, const wdlb_request *req, uint64_t *id);
+/* The request's state; when finished and h_ux_z is not NULL, its plane means
+ * <u_x>_xy (H values, FP64). */
+wdlb_status wdlb_server_poll(wdlb_server *srv, uint64_t id, wdlb_result *res, double *h_ux_z);
+/* Block until every submitted request has finished. */
+wdlb_status wdlb_server_drain(wdlb_server *srv);
+wdlb_status wdlb_server_stats_get(wdlb_server *srv, wdlb_server_stats *st);
+const char *wdlb_server_last_error(wdlb_server *srv);
+/* Stop the worker (requests not finished are abandoned) and release the
+ * server (host memory; the pool stays the caller's). */
+void wdlb_server_destroy(wdlb_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,11 +99,28 @@ __device__ __forceinline__ R pterm(int a, R ux, R uy, R uz)
     return R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
 }
 
+// One z-plane of a lattice of stacked slits (the serving lattice): fluid or
+// a solid gap between two slits; fluid planes carry their slit's body force
+// and relaxation (omega = 1/tau, ksrc = 1 - 1/(2 tau)).
+struct ZPlane {
+    double gx, gy, gz, omega, ksrc;
+    int fluid, pad0, pad1, pad2, pad3, pad4;
+};
+
 struct Geom {
     int nx, ny, nz, walls;
     long long N;
-    int tiny;  // 1 when an axis is shorter than the stencil reach: wrap by modulo
+    int tiny;              // 1 when an axis is shorter than the stencil reach: wrap by modulo
+    const ZPlane *zp;      // per-plane table of a stacked lattice, or null (one slit)
 };
+
+// the plane z (in range when periodic) holds fluid: between the walls, and
+// not a gap of a stacked lattice
+__device__ __forceinline__ bool zfluid(const Geom &g, int z)
+{
+    if (g.walls && (z < 0 || z >= g.nz)) return false;
+    return g.zp == nullptr || g.zp[z].fluid != 0;
+}
 
 __device__ __forceinline__ int wrap1(int v, int n)
 {

@@ -122,6 +122,18 @@ __device__ __forceinline__ void raise_flag(int *flag, int bit)
     __hip_atomic_fetch_or(flag, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// the body force of plane z: the slit's own in a stacked lattice, else the
+// lattice's (passed in)
+template <typename R>
+__device__ __forceinline__ void plane_force(const Geom &g, int z, R &gx, R &gy, R &gz)
+{
+    if (g.zp != nullptr) {
+        gx = R(g.zp[z].gx);
+        gy = R(g.zp[z].gy);
+        gz = R(g.zp[z].gz);
+    }
+}
+
 __device__ __forceinline__ bool node_of(const Geom &g, long long i, int &x, int &y, int &z)
 {
     if (i >= g.N) return false;
@@ -183,7 +195,7 @@ __device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, 
     int sz = z - CZ[a];
     bool bb = false;
     if (CZ[a] != 0) {
-        if (g.walls) bb = (sz < 0 || sz >= g.nz);
+        if (g.walls) bb = !zfluid(g, sz);
         else sz = wrap1(sz, g.nz);
     }
     int s, ha;
@@ -223,11 +235,13 @@ __device__ __forceinline__ void pull_moments(const Geom &g, const V4<R> *__restr
 // ---------------------------------------------------------------------------
 // step 1 (initialisation)
 // ---------------------------------------------------------------------------
+// nodes i0 .. i0 + cnt - 1 (a whole lattice, or the planes of one slit of a
+// stacked lattice)
 template <typename R>
-__global__ __launch_bounds__(256) void k_fill(Geom g, V4<R> *ru, R n0, R ux, R uy, R uz)
+__global__ __launch_bounds__(256) void k_fill(Geom g, V4<R> *ru, R n0, R ux, R uy, R uz, long long i0, long long cnt)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < g.N) ru[i] = V4<R>{n0, ux, uy, uz};
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt) ru[i0 + t] = V4<R>{n0, ux, uy, uz};
 }
 
 // The populations at every node r are feq(n(r), u(r)).  The library stores
@@ -236,9 +250,12 @@ __global__ __launch_bounds__(256) void k_fill(Geom g, V4<R> *ru, R n0, R ux, R u
 // wall, the value that bounces back into s itself, feq_abar(n(s), u(s)); h
 // is that minus feq_a(n(s), u(s)).
 template <typename R, typename HS>
-__global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ ru, HS *__restrict__ h)
+__global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ ru, HS *__restrict__ h, long long i0,
+                                              long long cnt)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const long long i = i0 + t;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const V4<R> q = ru[i];
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ 
         int tz = z + CZ[a];
         bool bb = false;
         if (CZ[a] != 0) {
-            if (g.walls) bb = (tz < 0 || tz >= g.nz);
+            if (g.walls) bb = !zfluid(g, tz);
             else tz = wrap1(tz, g.nz);
         }
         D val;
@@ -283,6 +300,11 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, Pad p, const V4<R> *__r
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
+    if (!zfluid(g, z)) {  // a gap plane of a stacked lattice: rho = 0 for every stencil
+        for_images(g, p, x, y, z, [&](int k) { rho_p[k] = R(0); });
+        jx[i] = jy[i] = jz[i] = R(0);
+        return;
+    }
     D r, a, b, c;
     pull_moments<R, HS>(g, ru, h, x, y, z, r, a, b, c);
     if (!(r > D(0)) || !(r < D(INFINITY))) raise_flag(flag, FLAG_RHO);
@@ -350,7 +372,7 @@ __device__ __forceinline__ void density_gamma(const Geom &g, const Pad &p, int x
     constexpr int DX = 1, DY = TX + 1, DZ = (TX + 1) * (TY + 1);
     const R n000 = m0[0], n100 = m0[DX], n010 = m0[DY], n110 = m0[DX + DY];
     const R n001 = m0[DZ], n101 = m0[DZ + DX], n011 = m0[DZ + DY], n111 = m0[DZ + DY + DX];
-    const bool zin = !g.walls || z + 1 < g.nz;  // the upper corners lie in the slit
+    const bool zin = !g.walls || zfluid(g, z + 1);  // the upper corners lie in the slit
     R m[8];
     m[0] = n000;
     m[1] = (n000 + n100) * R(0.5);
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, c
         const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
         const int zz = tc.z0 + mz;
         R v = 0;
-        if (!g.walls || (zz >= 0 && zz < g.nz)) {
+        if (!g.walls || zfluid(g, zz)) {
             const R *c = win + mz * LXY + my * LX + mx;
             R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             int k = 0;
@@ -445,7 +467,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R
         const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
         const int zz = tc.z0 + mz;
         R v = 0;
-        if (!g.walls || (zz >= 0 && zz < g.nz)) {
+        if (!g.walls || zfluid(g, zz)) {
             const R *c = win + mz * LXY + my * LX + mx;  // corner of the lane's ball window
             R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             static_for<0, B::NB>([&](auto ki) __attribute__((always_inline)) {
@@ -765,9 +787,13 @@ __device__ __forceinline__ void mf_finish(const Geom &g, const Pad &p, int x, in
                                           V4<R> *__restrict__ fmf)
 {
     const int i = (z * g.ny + y) * g.nx + x;
-    const R inv = R(1) / rr;
-    const V4<R> v = {rr, jx[i] * inv + R(0.5) * (gx + Fx), jy[i] * inv + R(0.5) * (gy + Fy),
-                     jz[i] * inv + R(0.5) * (gz + Fz)};
+    V4<R> v = {R(0), R(0), R(0), R(0)};
+    if (zfluid(g, z)) {
+        plane_force(g, z, gx, gy, gz);
+        const R inv = R(1) / rr;
+        v = V4<R>{rr, jx[i] * inv + R(0.5) * (gx + Fx), jy[i] * inv + R(0.5) * (gy + Fy),
+                  jz[i] * inv + R(0.5) * (gz + Fz)};
+    }
     for_images(g, p, x, y, z, [&](int k) { ru1_p[k] = v; });
     fmf[i] = V4<R>{Fx, Fy, Fz, R(0)};
 }
@@ -781,6 +807,7 @@ __device__ __forceinline__ void sh_finish(const Geom &g, int x, int y, int z, R 
 {
     const long long N = g.N;
     const int i = (z * g.ny + y) * g.nx + x;
+    plane_force(g, z, gx, gy, gz);
     const V4<R> fm = fmf[i];
     Fo[i] = r0 * (gx + fm.x + cv * acc[0]);
     Fo[N + i] = r0 * (gy + fm.y + cv * acc[1]);
@@ -1022,6 +1049,7 @@ __global__ __launch_bounds__(256) void k_plainforce(Geom g, Pad p, const R *__re
     if (!node_of(g, i, x, y, z)) return;
     const R r = rho_p[pidx(p, x, y, z)];
     const long long N = g.N;
+    plane_force(g, z, gx, gy, gz);
     Fo[i] = r * gx;
     Fo[N + i] = r * gy;
     Fo[2 * N + i] = r * gz;
@@ -1043,6 +1071,14 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const long long N = g.N;
+    if (!zfluid(g, z)) {  // gap plane of a stacked lattice: no state
+        if (READ) u_rd[i] = u_rd[N + i] = u_rd[2 * N + i] = R(0);
+        return;
+    }
+    if (g.zp != nullptr) {
+        omega = R(g.zp[z].omega);
+        ksrc = R(g.zp[z].ksrc);
+    }
     const int r = (z * g.ny + y) * g.nx + x;
     // the 19 pulled populations, kept for the collision (moments summed in
     // the order of pull_moments)

@@ -49,6 +49,7 @@ struct wdlb_ctx {
     void *quads;
     int *qstart;
     int *ball;
+    ZPlane *zp_dev;                       // per-plane table (used by stacked lattices)
     int nq, nball, rb, reach;  // quad count; ball size and reach; shell reach
     int dtile;                 // k_density tile (index into DENSITY_TILES)
     double wS;         // 4 pi / |S|
@@ -139,7 +140,7 @@ Pad make_pad(const wdlb_lattice_desc *d, int P)
 
 struct Layout {
     size_t off_ru[2], off_h[2], off_rho_p, off_gam_p, off_ru1_p, off_j[3], off_fmf, off_F, off_A, off_urd,
-        off_rhord, off_planes, off_flag, off_quads, off_qstart, off_ball, total;
+        off_rhord, off_planes, off_flag, off_quads, off_qstart, off_ball, off_zp, total;
 };
 
 // the layout does not depend on sigma: padded arrays are sized for the
@@ -176,6 +177,7 @@ Layout layout(const wdlb_lattice_desc *d)
     L.off_quads = take(MAX_QUADS * sizeof(Quad<double>));
     L.off_qstart = take((2 * MAX_REACH + 2) * sizeof(int));
     L.off_ball = take(MAX_BALL * sizeof(int));
+    L.off_zp = take((size_t)d->nz * sizeof(ZPlane));
     L.total = o;
     return L;
 }
@@ -683,6 +685,7 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->g.walls = desc->walls_z ? 1 : 0;
     c->g.N = (long long)desc->nx * desc->ny * desc->nz;
     c->g.tiny = 0;
+    c->g.zp = nullptr;
     c->ws = (char *)d_workspace;
     c->ws_bytes = bytes;
     for (int b = 0; b < 2; ++b) {
@@ -707,6 +710,7 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->quads = c->ws + L.off_quads;
     c->qstart = (int *)(c->ws + L.off_qstart);
     c->ball = (int *)(c->ws + L.off_ball);
+    c->zp_dev = (ZPlane *)(c->ws + L.off_zp);
     c->cur = 0;
     c->step = 0;
     c->inited = false;
@@ -755,23 +759,23 @@ static wdlb_status do_init(wdlb_ctx *c, int uniform, const double u0[3], const d
     case WDLB_FP64:
         if (uniform)
             hipLaunchKernelGGL((k_fill<double>), grid, dim3(256), 0, c->stream, g, (V4<double> *)c->ru[0], n0, ux,
-                               uy, uz);
+                               uy, uz, 0LL, g.N);
         hipLaunchKernelGGL((k_init<double, double>), grid, dim3(256), 0, c->stream, g,
-                           (const V4<double> *)c->ru[0], (double *)c->h[0]);
+                           (const V4<double> *)c->ru[0], (double *)c->h[0], 0LL, g.N);
         break;
     case WDLB_FP32:
         if (uniform)
             hipLaunchKernelGGL((k_fill<float>), grid, dim3(256), 0, c->stream, g, (V4<float> *)c->ru[0],
-                               (float)n0, (float)ux, (float)uy, (float)uz);
+                               (float)n0, (float)ux, (float)uy, (float)uz, 0LL, g.N);
         hipLaunchKernelGGL((k_init<float, float>), grid, dim3(256), 0, c->stream, g, (const V4<float> *)c->ru[0],
-                           (float *)c->h[0]);
+                           (float *)c->h[0], 0LL, g.N);
         break;
     default:
         if (uniform)
             hipLaunchKernelGGL((k_fill<float>), grid, dim3(256), 0, c->stream, g, (V4<float> *)c->ru[0],
-                               (float)n0, (float)ux, (float)uy, (float)uz);
+                               (float)n0, (float)ux, (float)uy, (float)uz, 0LL, g.N);
         hipLaunchKernelGGL((k_init<float, bf16>), grid, dim3(256), 0, c->stream, g, (const V4<float> *)c->ru[0],
-                           (bf16 *)c->h[0]);
+                           (bf16 *)c->h[0], 0LL, g.N);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1043,3 +1047,6 @@ void wdlb_destroy(wdlb_ctx *c)
 }
 
 }  // extern "C"
+
+// the serving loop (uses the context internals above)
+#include "server.hpp"

@@ -31,7 +31,9 @@ SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_set_params", "wdlb_init_u
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
            "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
-           "wdlb_get_tile", "wdlb_last_error", "wdlb_destroy"]
+           "wdlb_get_tile", "wdlb_last_error", "wdlb_destroy",
+           "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
+           "wdlb_server_drain", "wdlb_server_stats_get", "wdlb_server_last_error", "wdlb_server_destroy"]
 
 
 class LatticeDesc(C.Structure):
@@ -42,6 +44,27 @@ class LatticeDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma", C.c_double), ("eta", C.c_double), ("tau", C.c_double), ("g", C.c_double * 3),
                 ("nonlocal_", C.c_int32), ("smdb", C.c_int32)]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("tol", C.c_double), ("check_every", C.c_int32), ("pad", C.c_int32),
+                ("max_steps", C.c_int64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("H", C.c_int32), ("pad", C.c_int32), ("eta", C.c_double), ("gx", C.c_double), ("tau", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("H", C.c_int32), ("pad", C.c_int32),
+                ("steps", C.c_int64), ("j_pore", C.c_double), ("u_pore", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("chunks", C.c_int64), ("steps", C.c_int64), ("node_updates", C.c_double),
+                ("resident", C.c_int32), ("max_resident", C.c_int32), ("queued", C.c_int32),
+                ("finished", C.c_int32), ("busy_s", C.c_double)]
 
 
 class WdlbError(RuntimeError):
@@ -90,6 +113,17 @@ def load(path: str = LIB_PATH):
     L.wdlb_last_error.restype = C.c_char_p
     L.wdlb_destroy.argtypes = [vp]
     L.wdlb_destroy.restype = None
+    L.wdlb_server_workspace_size.argtypes = [C.POINTER(LatticeDesc), C.POINTER(ServerParams), C.POINTER(C.c_size_t)]
+    L.wdlb_server_create.argtypes = [C.POINTER(LatticeDesc), C.POINTER(ServerParams), vp, C.c_size_t,
+                                     C.POINTER(vp)]
+    L.wdlb_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    L.wdlb_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result), dp]
+    L.wdlb_server_drain.argtypes = [vp]
+    L.wdlb_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    L.wdlb_server_last_error.argtypes = [vp]
+    L.wdlb_server_last_error.restype = C.c_char_p
+    L.wdlb_server_destroy.argtypes = [vp]
+    L.wdlb_server_destroy.restype = None
     _lib = L
     return L
 
@@ -257,3 +291,66 @@ class Context:
         s = C.c_int64()
         self._chk(self._L.wdlb_get_step(self.h, C.byref(s)), "get_step")
         return s.value
+
+
+class Server:
+    """Batched slit-pore solves over resident requests (wdlb_server_*): nx x ny
+    slits of any height up to nz - R stacked in one lattice of nz planes; the
+    pool is a torch uint8 tensor; a worker thread in the library steps them."""
+
+    def __init__(self, nx, ny, nz, sigma=4.0, tol=1e-8, check_every=100, max_steps=100000, device="cuda"):
+        import torch
+        L = load()
+        self.desc = make_desc(nx, ny, nz, True, "fp32", None)
+        self.params = ServerParams(float(sigma), float(tol), int(check_every), 0, int(max_steps))
+        n = C.c_size_t(0)
+        st = L.wdlb_server_workspace_size(C.byref(self.desc), C.byref(self.params), C.byref(n))
+        if st != OK:
+            raise WdlbError(st, "wdlb_server_workspace_size")
+        self.pool = torch.empty(n.value, dtype=torch.uint8, device=device)
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        st = L.wdlb_server_create(C.byref(self.desc), C.byref(self.params), C.c_void_p(self.pool.data_ptr()),
+                                  n.value, C.byref(h))
+        if st != OK:
+            raise WdlbError(st, "wdlb_server_create")
+        self.h, self._L = h, L
+        self.sigma = float(sigma)
+
+    def submit(self, H, eta, gx, tau=1.0):
+        rid = C.c_uint64()
+        r = Request(int(H), 0, float(eta), float(gx), float(tau))
+        st = self._L.wdlb_server_submit(self.h, C.byref(r), C.byref(rid))
+        if st != OK:
+            raise WdlbError(st, f"submit: {self._L.wdlb_server_last_error(self.h).decode()}")
+        return rid.value
+
+    def poll(self, rid, H=None):
+        """(Result, u_x(z) plane means or None)."""
+        res = Result()
+        ux = np.zeros(H) if H else None
+        st = self._L.wdlb_server_poll(self.h, int(rid), C.byref(res), _ptr(ux) if ux is not None else None)
+        if st != OK:
+            raise WdlbError(st, "poll")
+        return res, (ux if res.state == 2 else None)
+
+    def drain(self):
+        st = self._L.wdlb_server_drain(self.h)
+        if st != OK:
+            raise WdlbError(st, f"drain: {self._L.wdlb_server_last_error(self.h).decode()}")
+
+    def stats(self):
+        s = ServerStats()
+        self._L.wdlb_server_stats_get(self.h, C.byref(s))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self._L.wdlb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

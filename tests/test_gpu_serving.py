@@ -1,0 +1,95 @@
+"""The serving loop (wdlb_server_*): slit pores of different heights, packing
+fractions, forcings and relaxation times stacked in one lattice and stepped
+together.  Each result must be bit-identical alone and in a mix (no slit
+reads another's planes, and every node sums in a fixed order), must equal a
+plain single-slit context stepped as long, and must match the FP64 column
+oracle within the FP32 bar (1e-5 relative on u_x(z) and the pore flux).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.column1d import Column
+from paper_1304_7880_amd.workloads import packing_to_density
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 4.0
+# (H, eta, g_x, tau)
+REQS = [(8, 0.2, 1e-5, 1.0), (12, 0.3, 3e-6, 0.8), (20, 0.1, 1e-6, 1.0), (31, 0.25, 5e-6, 1.0)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _serve(reqs, Z, tol=1e-30, max_steps=1500, check_every=100):
+    from paper_1304_7880_amd import wdlb
+    srv = wdlb.Server(16, 16, Z, sigma=SIGMA, tol=tol, check_every=check_every, max_steps=max_steps)
+    ids = [srv.submit(*r) for r in reqs]
+    srv.drain()
+    out = [srv.poll(i, H=r[0]) for i, r in zip(ids, reqs)]
+    stats = srv.stats()
+    srv.destroy()
+    return out, stats
+
+
+def test_mix_equals_alone_and_matches_oracle():
+    _say("serving: mix of 4 slits, then each alone")
+    mix, st = _serve(REQS, 120)
+    assert st["max_resident"] == 4 and st["finished"] == 4
+    for r, (res, ux) in zip(REQS, mix):
+        H, eta, gx, tau = r
+        assert res.state == 2 and res.status in (0, 6), res.status   # converged or capped
+        (res1, ux1), = _serve([r], 60)[0]
+        assert res1.steps == res.steps
+        assert np.array_equal(ux, ux1) and res.j_pore == res1.j_pore and res.u_pore == res1.u_pore
+        col = Column(H, sigma=SIGMA, tau=tau, g=(gx, 0.0, 0.0))
+        col.init(np.full(H, packing_to_density(eta, SIGMA)), np.zeros((3, H)))
+        col.step(res.steps)
+        _, ux_o, J_o, _, _ = col.reduce()
+        e_u = float(np.abs(ux - ux_o).max() / np.abs(ux_o).max())
+        e_J = abs(res.j_pore - J_o) / abs(J_o)
+        _say(f"  H={H} steps={res.steps} u_x(z) rel {e_u:.2e} J rel {e_J:.2e}")
+        assert e_u < 1e-5 and e_J < 1e-5
+
+
+def test_server_slot_equals_plain_context():
+    from paper_1304_7880_amd import wdlb
+    H, eta, gx, tau = REQS[3]
+    (res, ux), = _serve([REQS[3], REQS[0]], 100, max_steps=700)[0][:1]
+    ctx = wdlb.Context(16, 16, H, True, "fp32", SIGMA, eta, tau, (gx, 0.0, 0.0))
+    ctx.init_uniform((0.0, 0.0, 0.0))
+    ctx.step(res.steps)
+    _, ux_c = ctx.read_profiles()
+    J_c, U_c, _ = ctx.read_flux()
+    ctx.destroy()
+    assert np.array_equal(ux, ux_c)
+    assert res.j_pore == J_c and res.u_pore == U_c
+
+
+def test_admission_waits_for_free_planes_and_reuses_them():
+    # 60 planes hold one slit of H <= 56 (gap R = 4) plus at most a small one
+    reqs = [(30, 0.2, 2e-6, 1.0), (40, 0.15, 1e-6, 1.0), (24, 0.3, 4e-6, 1.0), (8, 0.2, 1e-5, 1.0)]
+    out, st = _serve(reqs, 60, max_steps=600)
+    assert st["finished"] == 4 and st["max_resident"] <= 2
+    for r, (res, ux) in zip(reqs, out):
+        assert res.state == 2 and res.steps <= 600
+        (res1, ux1), = _serve([r], 60, max_steps=600)[0]
+        assert np.array_equal(ux, ux1) and res.j_pore == res1.j_pore
+    # the 40-plane slit cannot start before the 30-plane one has left
+    assert out[1][0].t_admit >= out[0][0].t_done or out[0][0].t_admit >= out[1][0].t_done
+
+
+def test_invalid_requests_are_refused():
+    from paper_1304_7880_amd import wdlb
+    srv = wdlb.Server(16, 16, 40, sigma=SIGMA)
+    with pytest.raises(wdlb.WdlbError):
+        srv.submit(37, 0.2, 1e-6, 1.0)      # H + gap > 40 planes
+    with pytest.raises(wdlb.WdlbError):
+        srv.submit(8, 0.2, 1e-6, 0.5)       # tau must exceed 1/2
+    with pytest.raises(wdlb.WdlbError):
+        srv.submit(8, 1.2, 1e-6, 1.0)       # packing fraction outside (0, 1)
+    srv.destroy()
