@@ -122,6 +122,14 @@ __device__ __forceinline__ void raise_flag(int *flag, int bit)
     __hip_atomic_fetch_or(flag, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// flag[0] for the lattice and, in a stacked lattice, flag[1 + z] for plane z
+// (which slit went bad)
+__device__ __forceinline__ void raise_flag_at(const Geom &g, int *flag, int z, int bit)
+{
+    raise_flag(flag, bit);
+    if (g.zp != nullptr) raise_flag(flag + 1 + z, bit);
+}
+
 // the body force of plane z: the slit's own in a stacked lattice, else the
 // lattice's (passed in)
 template <typename R>
@@ -307,7 +315,7 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, Pad p, const V4<R> *__r
     }
     D r, a, b, c;
     pull_moments<R, HS>(g, ru, h, x, y, z, r, a, b, c);
-    if (!(r > D(0)) || !(r < D(INFINITY))) raise_flag(flag, FLAG_RHO);
+    if (!(r > D(0)) || !(r < D(INFINITY))) raise_flag_at(g, flag, z, FLAG_RHO);
     const R rr = R(r);
     for_images(g, p, x, y, z, [&](int k) { rho_p[k] = rr; });
     jx[i] = R(a);
@@ -395,7 +403,7 @@ __device__ __forceinline__ void density_gamma(const Geom &g, const Pad &p, int x
             val[hi] = R(0);
         }
     }
-    if (bad) raise_flag(flag, FLAG_ETA);
+    if (bad) raise_flag_at(g, flag, z, FLAG_ETA);
     for_images(g, p, x, y, z, [&](int k) {
 #pragma unroll
         for (int hi = 0; hi < 8; ++hi) gam_p[(long long)hi * p.NP + k] = val[hi];

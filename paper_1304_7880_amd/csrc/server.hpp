@@ -45,6 +45,7 @@ struct wdlb_server {
         bool have_prev;
     };
     std::vector<Slot> active;
+    std::vector<std::pair<int, int>> to_clear;  // planes (first, count) of retired slits
 
     // shared state (under mu)
     struct Job {
@@ -134,10 +135,22 @@ void fail_all(wdlb_server *S, wdlb_status st, const std::string &msg)
 // GPU part of one round (worker, without the lock): upload the plane table,
 // initialise the fresh slits, step, and take plane sums and the flag
 wdlb_status server_round(wdlb_server *S, const std::vector<wdlb_server::Slot> &fresh, std::vector<double> &sums,
-                         int &flag)
+                         std::vector<int> &flags)
 {
     wdlb_ctx *c = S->ctx;
     const Geom g = c->g;
+    // the padded fields of retired slits back to zero: planes above the run
+    // extent are not rewritten by the step, and a slit admitted next to them
+    // must see rho = 0 (and finite values) there
+    const Pad &pd = c->pad;
+    for (const auto &r : S->to_clear) {
+        const size_t at = (size_t)(r.first + pd.P) * pd.PXY, n = (size_t)r.second * pd.PXY;
+        HIPCHK(c, hipMemsetAsync((float *)c->rho_p + at, 0, n * sizeof(float), c->stream));
+        HIPCHK(c, hipMemsetAsync((V4<float> *)c->ru1_p + at, 0, n * sizeof(V4<float>), c->stream));
+        for (int h = 0; h < 8; ++h)
+            HIPCHK(c, hipMemsetAsync((float *)c->gam_p + (size_t)h * pd.NP + at, 0, n * sizeof(float), c->stream));
+    }
+    S->to_clear.clear();
     HIPCHK(c, hipMemcpyAsync(c->zp_dev, S->zp.data(), S->zp.size() * sizeof(ZPlane), hipMemcpyHostToDevice,
                              c->stream));
     for (const auto &s : fresh) {
@@ -149,19 +162,29 @@ wdlb_status server_round(wdlb_server *S, const std::vector<wdlb_server::Slot> &f
                            (const V4<float> *)c->ru[c->cur], (float *)c->h[c->cur], i0, cnt);
     }
     HIPCHK(c, hipGetLastError());
+    // process the planes up to the highest resident slit's trailing gap: no
+    // fluid stencil reaches beyond that gap
+    int top = 1;
+    for (int z = S->Z - 1; z >= 0; --z)
+        if (S->used[z]) {
+            top = z + 1;
+            break;
+        }
+    c->nz_run = top;
     wdlb_status st = wdlb_step(c, S->sp.check_every);
     if (st != WDLB_OK) return st;
     st = pass<true>(c);
     if (st != WDLB_OK) return st;
-    hipLaunchKernelGGL((k_planes<float>), dim3(g.nz), dim3(256), 0, c->stream, g, c->pad, (const float *)c->rho_p,
+    hipLaunchKernelGGL((k_planes<float>), dim3(top), dim3(256), 0, c->stream, g, c->pad, (const float *)c->rho_p,
                        (const float *)c->u_rd, c->planes);
     HIPCHK(c, hipGetLastError());
     sums.assign(3 * (size_t)g.nz, 0.0);
     HIPCHK(c, hipMemcpyAsync(sums.data(), c->planes, sums.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    flags.assign(1 + (size_t)g.nz, 0);
+    HIPCHK(c, hipMemcpyAsync(flags.data(), c->flag, flags.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (flag) {
-        HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    if (flags[0]) {
+        HIPCHK(c, hipMemsetAsync(c->flag, 0, flags.size() * sizeof(int), c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return WDLB_OK;
@@ -209,8 +232,8 @@ void serve(wdlb_server *S)
         lk.unlock();
         const double tb = S->now();
         std::vector<double> sums;
-        int flag = 0;
-        const wdlb_status st = server_round(S, fresh, sums, flag);
+        std::vector<int> flags;
+        const wdlb_status st = server_round(S, fresh, sums, flags);
         const double te = S->now();
         lk.lock();
         if (st != WDLB_OK) {
@@ -242,7 +265,8 @@ void serve(wdlb_server *S)
             }
             J /= S->plane * s.H;
             U /= s.H;
-            const bool bad = !std::isfinite(J) || !std::isfinite(U) || !(M > 0);
+            bool bad = !std::isfinite(J) || !std::isfinite(U) || !(M > 0);
+            for (int k = 0; k < s.H; ++k) bad = bad || flags[1 + s.z0 + k] != 0;
             const bool conv = s.have_prev && std::fabs(J - s.Jprev) <= S->sp.tol * std::fabs(J);
             wdlb_status fst = WDLB_OK;
             bool done = false;
@@ -261,6 +285,7 @@ void serve(wdlb_server *S)
                     S->used[z] = 0;
                     S->zp[z] = ZPlane{};
                 }
+                S->to_clear.push_back({s.z0, s.H + S->gap});
             } else {
                 s.Jprev = J;
                 s.have_prev = true;
@@ -268,17 +293,6 @@ void serve(wdlb_server *S)
             }
         }
         S->active.swap(keep);
-        // a flag that no slit's own sums explain fails every resident slit
-        if (flag && !S->active.empty()) {
-            for (auto &s : S->active) {
-                finish(S, s.id, WDLB_E_UNSTABLE, s.steps, 0, 0, {});
-                for (int z = s.z0; z < s.z0 + s.H + S->gap; ++z) {
-                    S->used[z] = 0;
-                    S->zp[z] = ZPlane{};
-                }
-            }
-            S->active.clear();
-        }
         S->stats.resident = (int32_t)S->active.size();
         S->stats.queued = (int32_t)S->queue.size();
         S->cv_done.notify_all();
@@ -331,7 +345,7 @@ wdlb_status wdlb_server_create(const wdlb_lattice_desc *desc, const wdlb_server_
     c->step = 0;
     if (hipMemcpyAsync(c->zp_dev, S->zp.data(), S->zp.size() * sizeof(ZPlane), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
-        hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->flag, 0, sizeof(int) * (1 + (size_t)S->Z), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         wdlb_destroy(c);
         (void)hipStreamDestroy(S->stream);

@@ -58,6 +58,7 @@ struct wdlb_ctx {
     int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
     int spec_b2;       // 2 sigma of the specialised density kernel in use, 0 = generic
     int cur;
+    int nz_run;        // planes the step kernels process (nz; fewer in a partly filled stacked lattice)
     int64_t step;
     bool inited;
     std::string err;
@@ -173,7 +174,7 @@ Layout layout(const wdlb_lattice_desc *d)
     L.off_urd = take(3 * r * N);
     L.off_rhord = take(r * N);
     L.off_planes = take(3 * sizeof(double) * (size_t)d->nz);
-    L.off_flag = take(256);
+    L.off_flag = take(sizeof(int) * (1 + (size_t)d->nz));  // lattice flag, then one per plane
     L.off_quads = take(MAX_QUADS * sizeof(Quad<double>));
     L.off_qstart = take((2 * MAX_REACH + 2) * sizeof(int));
     L.off_ball = take(MAX_BALL * sizeof(int));
@@ -403,7 +404,7 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
     const Geom g = c->g;
     const wdlb_params &p = c->prm;
     const double s = p.sigma;
-    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (c->nz_run + TZ - 1) / TZ;
     const dim3 grid(tx * ty * tz), block(TX * TY * TZ);
     const size_t lmf = shell_lds_bytes(TX, TY, TZ, c->reach, sizeof(R), sizeof(R), NG > 0);
     const size_t lsh = shell_lds_bytes(TX, TY, TZ, c->reach, sizeof(V4<R>), sizeof(R), NG > 0);
@@ -443,7 +444,7 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
         const Geom g = c->g;
         const wdlb_params &p = c->prm;
         const double s = p.sigma;
-        const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+        const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (c->nz_run + TZ - 1) / TZ;
         const dim3 grid(tx * ty * tz), block(TX * TY * TZ);
         const size_t lmf = shell_lds_bytes(TX, TY, TZ, RC, sizeof(R), sizeof(R), true);
         const size_t lsh = shell_lds_bytes(TX, TY, TZ, RC, sizeof(V4<R>), sizeof(R), true);
@@ -494,7 +495,7 @@ wdlb_status launch_density_g(wdlb_ctx *c)
 {
     const Geom g = c->g;
     const double s = c->prm.sigma;
-    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (c->nz_run + TZ - 1) / TZ;
     const size_t lds = density_lds_bytes(TX, TY, TZ, c->rb, sizeof(R));
     auto kern = k_density<R, TX, TY, TZ>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -518,7 +519,7 @@ wdlb_status launch_density_s(wdlb_ctx *c)
         return fail(c, WDLB_E_STATE, "compiled ball does not match the ball of sigma");
     const Geom g = c->g;
     const double s = c->prm.sigma;
-    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (c->nz_run + TZ - 1) / TZ;
     const size_t lds = density_lds_bytes(TX, TY, TZ, RB, sizeof(R));
     auto kern = k_density_s<R, S2, TX, TY, TZ>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -551,7 +552,7 @@ wdlb_status run_pass(wdlb_ctx *c)
     const Geom g = c->g;
     const Pad pd = c->pad;
     const int bs = 256;
-    dim3 grid = grid1(g.N, bs);
+    dim3 grid = grid1((long long)g.nx * g.ny * c->nz_run, bs);  // planes 0 .. nz_run - 1
     const int cur = c->cur, nxt = cur ^ 1;
     auto *ru_in = (const V4<R> *)c->ru[cur];
     auto *h_in = (const HS *)c->h[cur];
@@ -686,6 +687,7 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->g.N = (long long)desc->nx * desc->ny * desc->nz;
     c->g.tiny = 0;
     c->g.zp = nullptr;
+    c->nz_run = desc->nz;
     c->ws = (char *)d_workspace;
     c->ws_bytes = bytes;
     for (int b = 0; b < 2; ++b) {

@@ -93,3 +93,36 @@ def test_invalid_requests_are_refused():
     with pytest.raises(wdlb.WdlbError):
         srv.submit(8, 1.2, 1e-6, 1.0)       # packing fraction outside (0, 1)
     srv.destroy()
+
+
+def test_unstable_request_fails_alone():
+    """eta = 0.45 at sigma = 4 is outside the explicit scheme's range
+    (kappa > 2): that request ends WDLB_E_UNSTABLE; its neighbour in the same
+    lattice is unaffected (bit-identical to its run alone)."""
+    from paper_1304_7880_amd import wdlb
+    good, bad = (12, 0.2, 2e-6, 1.0), (16, 0.45, 1e-6, 1.0)
+    out, st = _serve([bad, good], 80, max_steps=3000)
+    (res_b, _), (res_g, ux_g) = out
+    _say(f"  unstable request: status {res_b.status} after {res_b.steps} steps; stable: {res_g.status}")
+    assert res_b.state == 2 and res_b.status == wdlb.E_UNSTABLE
+    assert res_g.state == 2 and res_g.status in (0, 6)
+    (res1, ux1), = _serve([good], 80, max_steps=3000)[0]
+    assert res1.steps == res_g.steps and np.array_equal(ux_g, ux1)
+
+
+def test_planes_of_a_failed_request_are_reused_cleanly():
+    """A later request placed on the planes of a request that went unstable
+    (non-finite values) gives the same result as alone."""
+    from paper_1304_7880_amd import wdlb
+    srv = wdlb.Server(16, 16, 60, sigma=SIGMA, tol=1e-30, check_every=100, max_steps=800)
+    first = [srv.submit(8, 0.2, 1e-5, 1.0), srv.submit(16, 0.45, 1e-6, 1.0)]
+    srv.drain()
+    assert srv.poll(first[1])[0].status == wdlb.E_UNSTABLE
+    late = (20, 0.25, 3e-6, 1.0)
+    rid = srv.submit(*late)
+    srv.drain()
+    res, ux = srv.poll(rid, H=late[0])
+    srv.destroy()
+    (res1, ux1), = _serve([late], 60, max_steps=800)[0]
+    assert res.status == res1.status and res.steps == res1.steps
+    assert np.all(np.isfinite(ux)) and np.array_equal(ux, ux1)
