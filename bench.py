@@ -101,12 +101,100 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       f"{dt:.1f} s, OpenMP over z-planes"}
 
 
+def _percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serving_bench(n_req, planes, max_steps, plain=True):
+    """Replay the first n_req requests of the seeded serving trace (Poisson
+    arrivals at 200/s, H in 8..96, eta in [0.05, 0.45], g_x log-uniform in
+    [1e-7, 1e-5], 16x16 in x,y, sigma = 4, tau = 1; steady when the pore flux
+    changes by < 1e-8 over 100 steps) in real time through the batched server
+    and through the plain loop (one single-slit context at a time, FIFO, the
+    same kernels and the same steady-state test)."""
+    import numpy as np
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import serving_requests
+
+    reqs = serving_requests(n=n_req)
+    tol, every, sigma = 1e-8, 100, 4.0
+
+    srv = wdlb.Server(16, 16, planes, sigma=sigma, tol=tol, check_every=every, max_steps=max_steps)
+    t0 = time.perf_counter()
+    ids = []
+    for r in reqs:
+        dt = r.arrival_s - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.submit(r.H, r.eta, r.gx, r.tau))
+    srv.drain()
+    res_b = [srv.poll(i, H=r.H) for i, r in zip(ids, reqs)]
+    st = srv.stats()
+    srv.destroy()
+    lat_b = [res.t_done - res.t_submit for res, _ in res_b]
+    span_b = max(res.t_done for res, _ in res_b) - min(res.t_submit for res, _ in res_b)
+    ok_b = [res.status == wdlb.OK for res, _ in res_b]
+    out = {"requests": n_req, "server_planes": planes,
+           "batched": {"solves_per_s": round(n_req / span_b, 3), "makespan_s": round(span_b, 3),
+                       "p50_latency_s": round(_percentile(lat_b, 50), 4),
+                       "p99_latency_s": round(_percentile(lat_b, 99), 4),
+                       "converged": int(sum(ok_b)),
+                       "unstable": int(sum(res.status == wdlb.E_UNSTABLE for res, _ in res_b)),
+                       "not_converged": int(sum(res.status == wdlb.E_NOT_CONVERGED for res, _ in res_b)),
+                       "max_resident": st["max_resident"],
+                       "mlups": round(st["node_updates"] / max(st["busy_s"], 1e-9) / 1e6, 1)}}
+    if not plain:
+        return out
+
+    t0 = time.perf_counter()
+    lat_p, same, t_last = [], True, 0.0
+    for r, (rb, uxb) in zip(reqs, res_b):
+        now = time.perf_counter() - t0
+        if now < r.arrival_s:
+            time.sleep(r.arrival_s - now)
+        ctx = wdlb.Context(16, 16, r.H, True, "fp32", sigma, r.eta, r.tau, (r.gx, 0.0, 0.0))
+        ctx.init_uniform((0.0, 0.0, 0.0))
+        steps, Jprev, status, J = 0, None, wdlb.OK, 0.0
+        while True:
+            ctx.step(every)
+            steps += every
+            try:
+                J, _, _ = ctx.read_flux()
+            except wdlb.WdlbError as e:
+                status = e.status
+                break
+            if Jprev is not None and abs(J - Jprev) <= tol * abs(J):
+                break
+            if steps >= max_steps:
+                status = wdlb.E_NOT_CONVERGED
+                break
+            Jprev = J
+        ctx.destroy()
+        t_last = time.perf_counter() - t0
+        lat_p.append(t_last - r.arrival_s)
+        same = same and status == rb.status and steps == rb.steps and (status != wdlb.OK or J == rb.j_pore)
+    span_p = t_last - reqs[0].arrival_s
+    out["plain"] = {"solves_per_s": round(n_req / span_p, 3), "makespan_s": round(span_p, 3),
+                    "p50_latency_s": round(_percentile(lat_p, 50), 4),
+                    "p99_latency_s": round(_percentile(lat_p, 99), 4)}
+    out["speedup_solves_per_s"] = round(out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"], 2)
+    out["results_identical_batched_vs_plain"] = bool(same)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serving", type=int, default=64, metavar="N",
+                    help="requests of the serving trace replayed through the batched server and the plain loop "
+                         "(0: skip)")
+    ap.add_argument("--serving-planes", type=int, default=4096, help="z-planes of the serving lattice")
+    ap.add_argument("--serving-max-steps", type=int, default=200000)
+    ap.add_argument("--serving-no-plain", action="store_true", help="batched server only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
                          "calibrating HBM byte counters under a profiler)")
@@ -201,10 +289,13 @@ def main():
         "wall_s": round(wall, 4),
         "pore_flux": J,
     }
+    ctx.destroy()
+    if args.serving:
+        out["serving"] = serving_bench(args.serving, args.serving_planes, args.serving_max_steps,
+                                       plain=not args.serving_no_plain)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
-    ctx.destroy()
 
 
 if __name__ == "__main__":

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/wdlb.h"
@@ -222,33 +223,38 @@ std::vector<Quad<R>> build_quads(double sigma, int &nshell)
     return v;
 }
 
-// Contact-shell tile variants (k_meanfield and k_shell use the same one),
-// tried in this order: 32 x 8 x 2 tiles with both LDS rings for growing
-// reach, a 32 x 16 x 1 tile, and a 16 x 16 x 1 tile that reads gamma through
-// L1/L2 (NG = 0).  NR / NG are the plane / gamma-slice elements each thread
-// stages.
+// Contact-shell tile variants (k_meanfield and k_shell use the same one).
+// Wide lattices try, in this order, 32 x 8 x 2 tiles with both LDS rings for
+// growing reach, a 32 x 16 x 1 tile, and a 16 x 16 x 1 tile that reads gamma
+// through L1/L2 (NG = 0).  Lattices at most 16 nodes wide in x (the stacked
+// serving lattice) take the 16 x 16 x 2 tile when it fits, so no lane of a
+// 32-wide row idles.  NR / NG are the plane / gamma-slice elements each
+// thread stages.
 struct ShellTile {
     int TX, TY, TZ, NR, NG;
 };
 constexpr ShellTile SHELL_TILES[] = {{32, 8, 2, 2, 5}, {32, 8, 2, 3, 6}, {32, 8, 2, 4, 8}, {32, 16, 1, 7, 13},
-                                     {16, 16, 1, 10, 0}};
+                                     {16, 16, 1, 10, 0}, {16, 16, 2, 2, 5}};
+constexpr int NARROW_TILE = 5;  // the 16 x 16 x 2 variant
 constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
 static_assert(NTILES == WDLB_NTILES, "the header's variant count");
 constexpr size_t LDS_MAX = 160 * 1024;
 
 // k_density tiles: 32 x 8 x 2 while its LDS stays within 64 KB (several
-// blocks per CU), else 16 x 8 x 1
+// blocks per CU), else 16 x 8 x 1; lattices at most 16 wide take 16 x 16 x 2
 struct DensityTile {
     int TX, TY, TZ;
     size_t lds_cap;
 };
-constexpr DensityTile DENSITY_TILES[2] = {{32, 8, 2, 64 * 1024}, {16, 8, 1, 160 * 1024}};
+constexpr DensityTile DENSITY_TILES[3] = {{32, 8, 2, 64 * 1024}, {16, 8, 1, 160 * 1024}, {16, 16, 2, 64 * 1024}};
+constexpr int NARROW_DENSITY_TILE = 2;
 constexpr bool density_fits(const DensityTile &t, int rb, size_t rbytes)
 {
     return density_lds_bytes(t.TX, t.TY, t.TZ, rb, rbytes) <= t.lds_cap;
 }
-constexpr int pick_density_tile(int rb, size_t rbytes)
+constexpr int pick_density_tile(int rb, size_t rbytes, int nx)
 {
+    if (nx <= 16 && density_fits(DENSITY_TILES[NARROW_DENSITY_TILE], rb, rbytes)) return NARROW_DENSITY_TILE;
     return density_fits(DENSITY_TILES[0], rb, rbytes) ? 0 : (density_fits(DENSITY_TILES[1], rb, rbytes) ? 1 : -1);
 }
 
@@ -261,21 +267,45 @@ constexpr bool tile_fits(const ShellTile &t, int reach, size_t rbytes)
     return shell_lds_bytes(t.TX, t.TY, t.TZ, reach, 4 * rbytes, rbytes, t.NG > 0) <= LDS_MAX;
 }
 
-constexpr int pick_tile(int reach, size_t rbytes)
+// the automatic choice for wide lattices
+constexpr int pick_tile_wide(int reach, size_t rbytes)
 {
-    for (int k = 0; k < NTILES; ++k)
+    for (int k = 0; k < NARROW_TILE; ++k)
         if (tile_fits(SHELL_TILES[k], reach, rbytes)) return k;
     return -1;
 }
 
-// 2 sigma when the library holds shell kernels specialised for sigma
-// (those of the tile the automatic choice takes), else 0
+constexpr int pick_tile(int reach, size_t rbytes, int nx)
+{
+    if (nx <= 16 && tile_fits(SHELL_TILES[NARROW_TILE], reach, rbytes)) return NARROW_TILE;
+    return pick_tile_wide(reach, rbytes);
+}
+
+// 2 sigma of the shells and balls compiled into the library, else 0
 int specialised_s2(double sigma)
 {
     static const int S2[] = {6, 8, 12, 16, 20};
     for (int s2 : S2)
         if (sigma == 0.5 * s2) return s2;
     return 0;
+}
+
+// compiled kernels exist for the wide automatic tiles of every compiled
+// shell (when gamma is staged in LDS), and for the narrow tiles at sigma = 4
+// in FP32 (the serving configuration)
+template <typename R>
+bool compiled_shell(int s2, int tile, int reach)
+{
+    if (s2 == 0) return false;
+    if (tile == NARROW_TILE) return std::is_same<R, float>::value && s2 == 8;
+    return tile == pick_tile_wide(reach, sizeof(R)) && SHELL_TILES[tile].NG > 0;
+}
+template <typename R>
+bool compiled_density(int s2, int dtile, int rb)
+{
+    if (s2 == 0) return false;
+    if (dtile == NARROW_DENSITY_TILE) return std::is_same<R, float>::value && s2 == 8;
+    return dtile == pick_density_tile(rb, sizeof(R), 1 << 30);
 }
 
 template <typename R>
@@ -306,23 +336,23 @@ wdlb_status upload_tables(wdlb_ctx *c)
                 }
     if ((int)bx.size() > MAX_BALL) return fail(c, WDLB_E_INVAL, "stencil too large");
     if (rb + 1 > c->pad.P) return fail(c, WDLB_E_INVAL, "sigma too small for the padded arrays");
-    int dtile = -1;
-    for (int k = 0; k < 2 && dtile < 0; ++k)
-        if (density_fits(DENSITY_TILES[k], rb, sizeof(R))) dtile = k;
+    const int dtile = pick_density_tile(rb, sizeof(R), c->g.nx);
     if (dtile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the density tiles");
     // window offsets of the ball from the corner of a node's window
     const int LX = DENSITY_TILES[dtile].TX + 2 * rb + 1, LY = DENSITY_TILES[dtile].TY + 2 * rb + 1;
     std::vector<int> b(bx.size());
     for (size_t k = 0; k < bx.size(); ++k) b[k] = (bz[k] + rb) * LX * LY + (by[k] + rb) * LX + (bx[k] + rb);
     c->spec_s2 = 0;
-    c->spec_b2 = c->tile_req >= 0 ? 0 : specialised_s2(c->prm.sigma);
+    c->spec_b2 = 0;
+    const int s2c = specialised_s2(c->prm.sigma);
     if (c->tile_req >= 0) {
         if (!tile_fits(SHELL_TILES[c->tile_req], reach, sizeof(R)))
             return fail(c, WDLB_E_INVAL, "the requested shell tile does not fit this sigma");
         c->tile = c->tile_req;
     } else {
-        c->tile = pick_tile(reach, sizeof(R));
-        if (c->tile >= 0 && SHELL_TILES[c->tile].NG > 0) c->spec_s2 = specialised_s2(c->prm.sigma);
+        c->tile = pick_tile(reach, sizeof(R), c->g.nx);
+        if (c->tile >= 0 && compiled_shell<R>(s2c, c->tile, reach)) c->spec_s2 = s2c;
+        if (compiled_density<R>(s2c, dtile, rb)) c->spec_b2 = s2c;
     }
     if (c->tile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the shell tiles");
     HIPCHK(c, hipMemcpyAsync(c->quads, q.data(), q.size() * sizeof(Quad<R>), hipMemcpyHostToDevice, c->stream));
@@ -427,14 +457,13 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
     });
 }
 
-// the pair specialised for the shell 2 sigma = S2 on the tile that the
-// automatic choice takes for it
-template <typename R, int S2>
+// the pair specialised for the shell 2 sigma = S2 on tile TI
+template <typename R, int S2, int TI>
 wdlb_status launch_shell_pair_s(wdlb_ctx *c)
 {
     constexpr int RC = Shell<S2>::R;
-    constexpr int TI = pick_tile(RC, sizeof(R));
     static_assert(TI >= 0, "no tile for this shell");
+    if (c->tile != TI) return fail(c, WDLB_E_STATE, "compiled shell kernels are for another tile");
     constexpr ShellTile T = SHELL_TILES[TI];
     constexpr int TX = T.TX, TY = T.TY, TZ = T.TZ, NR = T.NR, NG = T.NG;
     if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
@@ -470,23 +499,28 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
 template <typename R>
 wdlb_status launch_shells(wdlb_ctx *c)
 {
+#define WDLB_WIDE(S2) launch_shell_pair_s<R, S2, pick_tile_wide(Shell<S2>::R, sizeof(R))>(c)
     if (c->spec_s2 > 0) {
+        if constexpr (std::is_same<R, float>::value)
+            if (c->tile == NARROW_TILE && c->spec_s2 == 8) return launch_shell_pair_s<R, 8, NARROW_TILE>(c);
         switch (c->spec_s2) {
-        case 6: return launch_shell_pair_s<R, 6>(c);
-        case 8: return launch_shell_pair_s<R, 8>(c);
-        case 12: return launch_shell_pair_s<R, 12>(c);
-        case 16: return launch_shell_pair_s<R, 16>(c);
-        case 20: return launch_shell_pair_s<R, 20>(c);
+        case 6: return WDLB_WIDE(6);
+        case 8: return WDLB_WIDE(8);
+        case 12: return WDLB_WIDE(12);
+        case 16: return WDLB_WIDE(16);
+        case 20: return WDLB_WIDE(20);
         default: break;
         }
     }
-    static_assert(NTILES == 5, "one case per entry of SHELL_TILES");
+#undef WDLB_WIDE
+    static_assert(NTILES == 6, "one case per entry of SHELL_TILES");
     switch (c->tile) {
     case 0: return launch_shell_pair<R, 32, 8, 2, 2, 5>(c);
     case 1: return launch_shell_pair<R, 32, 8, 2, 3, 6>(c);
     case 2: return launch_shell_pair<R, 32, 8, 2, 4, 8>(c);
     case 3: return launch_shell_pair<R, 32, 16, 1, 7, 13>(c);
-    default: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
+    case 4: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
+    default: return launch_shell_pair<R, 16, 16, 2, 2, 5>(c);
     }
 }
 
@@ -506,13 +540,11 @@ wdlb_status launch_density_g(wdlb_ctx *c)
     });
 }
 
-// specialised for the ball of 2 sigma = S2 on the tile the automatic choice
-// takes for it
-template <typename R, int S2>
+// specialised for the ball of 2 sigma = S2 on density tile DT
+template <typename R, int S2, int DT>
 wdlb_status launch_density_s(wdlb_ctx *c)
 {
     constexpr int RB = Ball<S2>::RB;
-    constexpr int DT = pick_density_tile(RB, sizeof(R));
     static_assert(DT >= 0, "no density tile for this ball");
     constexpr int TX = DENSITY_TILES[DT].TX, TY = DENSITY_TILES[DT].TY, TZ = DENSITY_TILES[DT].TZ;
     if (c->rb != RB || c->nball != Ball<S2>::NB || c->dtile != DT)
@@ -533,15 +565,24 @@ wdlb_status launch_density_s(wdlb_ctx *c)
 template <typename R>
 wdlb_status launch_density(wdlb_ctx *c)
 {
+#define WDLB_WIDE(S2) launch_density_s<R, S2, pick_density_tile(Ball<S2>::RB, sizeof(R), 1 << 30)>(c)
+    if constexpr (std::is_same<R, float>::value)
+        if (c->spec_b2 == 8 && c->dtile == NARROW_DENSITY_TILE)
+            return launch_density_s<R, 8, NARROW_DENSITY_TILE>(c);
     switch (c->spec_b2) {
-    case 6: return launch_density_s<R, 6>(c);
-    case 8: return launch_density_s<R, 8>(c);
-    case 12: return launch_density_s<R, 12>(c);
-    case 16: return launch_density_s<R, 16>(c);
-    case 20: return launch_density_s<R, 20>(c);
+    case 6: return WDLB_WIDE(6);
+    case 8: return WDLB_WIDE(8);
+    case 12: return WDLB_WIDE(12);
+    case 16: return WDLB_WIDE(16);
+    case 20: return WDLB_WIDE(20);
     default: break;
     }
-    return c->dtile == 0 ? launch_density_g<R, 32, 8, 2>(c) : launch_density_g<R, 16, 8, 1>(c);
+#undef WDLB_WIDE
+    switch (c->dtile) {
+    case 0: return launch_density_g<R, 32, 8, 2>(c);
+    case 1: return launch_density_g<R, 16, 8, 1>(c);
+    default: return launch_density_g<R, 16, 16, 2>(c);
+    }
 }
 
 // one pass of the step kernels on the current buffers; READ stops after the

@@ -45,6 +45,8 @@ CASES = [
     ("walled 17x5x23 sigma=6", (17, 5, 23), True, 6.0, 0.35, 0.8, (2e-5, 0, 0), 3),
     # fp64 at sigma = 8: the density kernel runs on its 16x8x1 tiles
     ("walled 12x9x21 sigma=8", (12, 9, 21), True, 8.0, 0.3, 0.9, (1e-4, 0, 0), 2),
+    # 16 wide in x: the narrow 16x16x2 tiles (compiled for sigma = 4 in fp32)
+    ("walled 16x16x14 sigma=4 (narrow tiles)", (16, 16, 14), True, 4.0, 0.3, 1.0, (2e-5, 0, 0), 3),
 ]
 
 
@@ -76,11 +78,11 @@ def test_random_fields_few_steps(case, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
-@pytest.mark.parametrize("variant", range(5))
+@pytest.mark.parametrize("variant", range(6))
 def test_shell_tile_variants(variant, prec, tol):
-    """Every contact-shell tile variant (LDS rings of 32x8x2, 32x16x1 and the
-    16x16x1 tile reading gamma through the caches), forced on a walled
-    40x20x13 lattice that leaves ragged tiles in x, y and z."""
+    """Every contact-shell tile variant (LDS rings of 32x8x2, 32x16x1 and
+    16x16x2, and the 16x16x1 tile reading gamma through the caches), forced
+    on a walled 40x20x13 lattice that leaves ragged tiles in x, y and z."""
     from paper_1304_7880_amd import wdlb
     nx, ny, nz, sigma, eta, tau, g = 40, 20, 13, 4.0, 0.3, 0.9, (1e-4, -3e-5, 0.0)
     _say(f"tile variant {variant} {prec}")
@@ -284,3 +286,28 @@ def test_slab64_full_size_first_steps():
     assert np.abs(ux_g - ux_o).max() < 1e-5 * np.abs(u_o).max()
     assert _rel(nz_g, nz_o) < 1e-6
     ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_narrow_tiles_compiled_equals_table_driven(prec):
+    """A lattice 16 wide takes the 16x16x2 tiles; at sigma = 4 in fp32 it runs
+    the compiled shell and ball, which must equal the table-driven kernels on
+    the same tile bit for bit."""
+    nx, ny, nz, sigma, eta, tau, g = 16, 16, 23, 4.0, 0.25, 1.0, (1e-5, 0.0, 0.0)
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=9)
+    out = []
+    for forced in (False, True):
+        ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, g)
+        tile, spec = ctx.get_tile()
+        assert tile == 5
+        if forced:
+            ctx.set_tile(5)
+            assert ctx.get_tile() == (5, False)
+        else:
+            assert spec == (prec == "fp32")
+        ctx.init_fields(n, u)
+        ctx.step(3)
+        out.append(ctx.read_fields(with_forces=True))
+        ctx.destroy()
+    for k, name in enumerate(("rho", "u", "F", "A0")):
+        assert np.array_equal(out[0][k], out[1][k]), (name, _rel(out[0][k], out[1][k]))
