@@ -410,6 +410,20 @@ __device__ __forceinline__ void density_gamma(const Geom &g, const Pad &p, int x
     });
 }
 
+// nbar over the (TX+1)(TY+1)(TZ+1) block: first the tile's TX columns (lanes
+// of a half-wave on one row of the window: no LDS bank conflicts), then the
+// extra column mx = TX
+template <int TX, int TY, int TZ, typename F>
+__device__ __forceinline__ void density_nbar_sweep(F &&nbar_at)
+{
+    constexpr int NT = TX * TY * TZ, MY = TY + 1, MZ = TZ + 1;
+    for (int e = threadIdx.x; e < TX * MY * MZ; e += NT) {
+        const int t = e / TX;
+        nbar_at(e % TX, t % MY, t / MY);
+    }
+    for (int e = threadIdx.x; e < MY * MZ; e += NT) nbar_at(TX, e % MY, e / MY);
+}
+
 // generic: the ball from its table of window offsets (relative to the
 // corner of a node's ball window; order z, then y, then x), summed into 8
 // interleaved partial sums, point k into sum k mod 8 (the order of the
@@ -429,8 +443,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, c
     R *nb = win + (size_t)LX * LY * LZ;
     density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
     __syncthreads();
-    for (int e = threadIdx.x; e < MN; e += NT) {
-        const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
+    auto nbar_at = [&](int mx, int my, int mz) {
         const int zz = tc.z0 + mz;
         R v = 0;
         if (!g.walls || zfluid(g, zz)) {
@@ -446,8 +459,9 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, c
                 if (k + m < nball) s[m] += c[boff[k + m]];
             v = (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))) * inv_nball;
         }
-        nb[e] = v;
-    }
+        nb[(mz * MY + my) * MX + mx] = v;
+    };
+    density_nbar_sweep<TX, TY, TZ>(nbar_at);
     __syncthreads();
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
@@ -471,8 +485,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R
     R *nb = win + (size_t)LX * LY * LZ;
     density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
     __syncthreads();
-    for (int e = threadIdx.x; e < MN; e += NT) {
-        const int mx = e % MX, t = e / MX, my = t % MY, mz = t / MY;
+    auto nbar_at = [&](int mx, int my, int mz) __attribute__((always_inline)) {
         const int zz = tc.z0 + mz;
         R v = 0;
         if (!g.walls || zfluid(g, zz)) {
@@ -484,8 +497,9 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R
             });
             v = (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))) * inv_nball;
         }
-        nb[e] = v;
-    }
+        nb[(mz * MY + my) * MX + mx] = v;
+    };
+    density_nbar_sweep<TX, TY, TZ>(nbar_at);
     __syncthreads();
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
