@@ -543,7 +543,7 @@ template <typename R, int NT, int NG>
 struct GammaRing {
     int LXg, LG, LS;
     int gh[NG], goff[NG];
-    R st[NG];
+    R st[2][NG];  // two staging sets: one in flight while the other is stored
 
     __device__ __forceinline__ void setup(const Pad &p, int Rr, int TX, int TY, int x0, int y0)
     {
@@ -561,20 +561,22 @@ struct GammaRing {
             goff[k] = Y * p.PX + X;
         }
     }
-    // slice t (plane z0 + floor(t/2), z-parity t & 1) into registers
+    // slice t (plane z0 + floor(t/2), z-parity t & 1) into staging set S
+    template <int S>
     __device__ __forceinline__ void fetch(const R *__restrict__ gam_p, const Pad &p, int z0, int t)
     {
         const int hz = t & 1;
         const long long zb = (long long)min(max(z0 + (t >> 1) + p.P, 0), p.PZ - 1) * p.PXY;
 #pragma unroll
-        for (int k = 0; k < NG; ++k) st[k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
+        for (int k = 0; k < NG; ++k) st[S][k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
     }
+    template <int S>
     __device__ __forceinline__ void store(R *win, int slot)
     {
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
             const int e = (int)threadIdx.x + k * NT;
-            if (e < LS) win[slot * LS + e] = st[k];
+            if (e < LS) win[slot * LS + e] = st[S][k];
         }
     }
 };
@@ -607,7 +609,7 @@ struct PlaneRing {
     static constexpr int NC = Comp<V>::n;
     int LX, LP;
     int off[NR];
-    R st[NC][NR];
+    R st[2][NC][NR];  // two staging sets: one in flight while the other is stored
 
     __device__ __forceinline__ void setup(const Pad &p, int Rr, int TX, int TY, int x0, int y0)
     {
@@ -621,6 +623,7 @@ struct PlaneRing {
             off[k] = Y * p.PX + X;
         }
     }
+    template <int S>
     __device__ __forceinline__ void fetch(const V *__restrict__ src, const Pad &p, int pz)
     {
         const long long zb = (long long)min(max(pz + p.P, 0), p.PZ - 1) * p.PXY;
@@ -628,9 +631,10 @@ struct PlaneRing {
         for (int k = 0; k < NR; ++k) {
             const V v = src[zb + off[k]];
 #pragma unroll
-            for (int m = 0; m < NC; ++m) st[m][k] = Comp<V>::get(v, m);
+            for (int m = 0; m < NC; ++m) st[S][m][k] = Comp<V>::get(v, m);
         }
     }
+    template <int S>
     __device__ __forceinline__ void store(V *win, int slot)
     {
 #pragma unroll
@@ -639,7 +643,7 @@ struct PlaneRing {
             if (e < LP) {
                 V v;
 #pragma unroll
-                for (int m = 0; m < NC; ++m) Comp<V>::set(v, m, st[m][k]);
+                for (int m = 0; m < NC; ++m) Comp<V>::set(v, m, st[S][m][k]);
                 win[slot * LP + e] = v;
             }
         }
@@ -655,12 +659,20 @@ __host__ __device__ constexpr size_t shell_lds_bytes(int TX, int TY, int TZ, int
            (gamma_lds ? (size_t)(2 * TZ) * 4 * (TX + Rr) * (TY + Rr) * rbytes : 0);
 }
 
-// Both rings of one block and the per-lane pointers into them.  A c-step is
-//   begin(c)  fetch the next plane and slice into registers (c < R),
-//   ...       sum the quads of e_z = c from plane(c) and gamma(c),
-//   end(c)    store the fetched entries into the free slots, barrier.
-template <typename R, typename V, int TX, int TY, int TZ, int NR, int NG>
+// Both rings of one block and the per-lane pointers into them.  With
+// prefetch depth PD = 1 a c-step is
+//   begin<S>(c)  fetch the plane and slice that step c + 1 will read,
+//   ...          sum the quads of e_z = c from plane(c) and gamma(c),
+//   end<S>(c)    store them into the free slots (those of the plane and
+//                slice last read at step c - 1), barrier.
+// With PD = 2 the fetches run one step earlier, into two register sets that
+// alternate with the parity S = (c + R) & 1 of the step: begin<S>(c)
+// fetches for step c + 2 into set S ^ 1 while set S holds what end<S>(c)
+// stores.  PD = 2 hides more load latency at the cost of registers (the
+// mean-field kernel, light on arithmetic per step, uses it).
+template <typename R, typename V, int TX, int TY, int TZ, int NR, int NG, int PD = 1>
 struct ShellRings {
+    static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2");
     static constexpr int NT = TX * TY * TZ, NS = TZ + 1, NSG = 2 * TZ;
     static constexpr bool GL = NG > 0;
     PlaneRing<R, V, NT, NR> pr;
@@ -687,29 +699,41 @@ struct ShellRings {
         }
 #pragma unroll
         for (int k = 0; k < TZ; ++k) {
-            pr.fetch(src, p, z0 - Rr + k);
-            pr.store(win, k);
+            pr.template fetch<0>(src, p, z0 - Rr + k);
+            pr.template store<0>(win, k);
         }
         if constexpr (GL) {
             for (int t = -Rr; t <= -Rr + 2 * TZ - 2; ++t) {
-                gr.fetch(gam_p, p, z0, t);
-                gr.store(gwin, (t + 64) % NSG);
+                gr.template fetch<0>(gam_p, p, z0, t);
+                gr.template store<0>(gwin, (t + 64) % NSG);
             }
+        }
+        if constexpr (PD == 2) {  // what step -R stores at its end
+            pr.template fetch<0>(src, p, z0 + TZ - Rr);
+            if constexpr (GL) gr.template fetch<0>(gam_p, p, z0, 2 * TZ - 1 - Rr);
         }
         __syncthreads();
     }
+    template <int S>
     __device__ __forceinline__ void begin(int c, const Pad &p, const V *__restrict__ src, const R *__restrict__ gam_p)
     {
-        if (c < Rr) {
-            pr.fetch(src, p, z0 + c + TZ);
-            if constexpr (GL) gr.fetch(gam_p, p, z0, c + 2 * TZ - 1);
+        if constexpr (PD == 2) {
+            if (c + 1 < Rr) {
+                pr.template fetch<S ^ 1>(src, p, z0 + c + 1 + TZ);
+                if constexpr (GL) gr.template fetch<S ^ 1>(gam_p, p, z0, c + 2 * TZ);
+            }
+        } else if (c < Rr) {
+            pr.template fetch<0>(src, p, z0 + c + TZ);
+            if constexpr (GL) gr.template fetch<0>(gam_p, p, z0, c + 2 * TZ - 1);
         }
     }
+    template <int S>
     __device__ __forceinline__ void end(int c)
     {
+        constexpr int SS = PD == 2 ? S : 0;
         if (c < Rr) {
-            pr.store(win, (c + TZ + Rr) % NS);
-            if constexpr (GL) gr.store(gwin, (c + 2 * TZ - 1 + 64) % NSG);
+            pr.template store<SS>(win, (c + TZ + Rr) % NS);
+            if constexpr (GL) gr.template store<SS>(gwin, (c + 2 * TZ - 1 + 64) % NSG);
         }
         __syncthreads();
     }
@@ -896,13 +920,14 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield(Geom g, Pad p, int Rr,
     const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
-    ShellRings<R, R, TX, TY, TZ, NR, NG> rg;
+    ShellRings<R, R, TX, TY, TZ, NR, NG, 2> rg;
     rg.init(lds_raw, p, Rr, tc, rho_p, gam_p);
     const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
     const int LX = rg.pr.LX;
     R fx = 0, fy = 0, fz = 0;
-    for (int c = -Rr; c <= Rr; ++c) {
-        rg.begin(c, p, rho_p, gam_p);
+    auto cstep = [&](auto si, int c) __attribute__((always_inline)) {
+        constexpr int S = decltype(si)::value;
+        rg.template begin<S>(c, p, rho_p, gam_p);
         const R *pl = rg.plane(c);
         const R *gl = GL ? rg.gamma(c) : nullptr;
         const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
@@ -917,7 +942,11 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield(Geom g, Pad p, int Rr,
             rm[3] = pl[-a - b * LX];
             mf_quad<R>(gm, rm, Qd.px, Qd.py, Qd.pz, fx, fy, fz);
         }
-        rg.end(c);
+        rg.template end<S>(c);
+    };
+    for (int c = -Rr; c <= Rr; c += 2) {
+        cstep(std::integral_constant<int, 0>{}, c);
+        if (c + 1 <= Rr) cstep(std::integral_constant<int, 1>{}, c + 1);
     }
     if (!valid) return;
     mf_finish<R>(g, p, x, y, z, rho_p[gbase], cmf * fx, cmf * fy, cmf * fz, jx, jy, jz, gx, gy, gz, ru1_p, fmf);
@@ -947,8 +976,9 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
     const V4<R> c0 = ru1_p[gbase];
     const int LX = rg.pr.LX;
     R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int c = -Rr; c <= Rr; ++c) {
-        rg.begin(c, p, ru1_p, gam_p);
+    auto cstep = [&](auto si, int c) __attribute__((always_inline)) {
+        constexpr int S = decltype(si)::value;
+        rg.template begin<S>(c, p, ru1_p, gam_p);
         const V4<R> *pl = rg.plane(c);
         const R *gl = GL ? rg.gamma(c) : nullptr;
         const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
@@ -964,7 +994,11 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
             sm[3] = pl[-a - b * LX];
             sh_quad<R>(gm, sm, c0, Qd.px, Qd.py, Qd.pz, Qd.qxx, Qd.qyy, Qd.qzz, Qd.qxy, Qd.qxz, Qd.qyz, acc);
         }
-        rg.end(c);
+        rg.template end<S>(c);
+    };
+    for (int c = -Rr; c <= Rr; c += 2) {
+        cstep(std::integral_constant<int, 0>{}, c);
+        if (c + 1 <= Rr) cstep(std::integral_constant<int, 1>{}, c + 1);
     }
     if (!valid) return;
     sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
@@ -991,12 +1025,13 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
     const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
-    ShellRings<R, R, TX, TY, TZ, NR, NG> rg;
+    ShellRings<R, R, TX, TY, TZ, NR, NG, 2> rg;
     rg.init(lds_raw, p, RC, tc, rho_p, gam_p);
     R fx = 0, fy = 0, fz = 0;
     static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
         constexpr int c = decltype(ci)::value;
-        rg.begin(c, p, rho_p, gam_p);
+        constexpr int S = (c + RC) & 1;
+        rg.template begin<S>(c, p, rho_p, gam_p);
         const R *pc = rg.plane(c) - (RC + RC * LX);
         const R *gc = rg.gamma(c) - (O + O * LXg);
         static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
@@ -1012,7 +1047,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
         pin(fx);
         pin(fy);
         pin(fz);
-        rg.end(c);
+        rg.template end<S>(c);
     });
     if (!valid) return;
     mf_finish<R>(g, p, x, y, z, rho_p[pidx(p, x, y, z)], cmf * fx, cmf * fy, cmf * fz, jx, jy, jz, gx, gy, gz,
@@ -1039,7 +1074,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
     R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
         constexpr int c = decltype(ci)::value;
-        rg.begin(c, p, ru1_p, gam_p);
+        constexpr int S = (c + RC) & 1;
+        rg.template begin<S>(c, p, ru1_p, gam_p);
         const V4<R> *pc = rg.plane(c) - (RC + RC * LX);
         const R *gc = rg.gamma(c) - (O + O * LXg);
         static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
@@ -1055,7 +1091,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
         });
 #pragma unroll
         for (int k = 0; k < 9; ++k) pin(acc[k]);
-        rg.end(c);
+        rg.template end<S>(c);
     });
     if (!valid) return;
     sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
