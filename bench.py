@@ -183,6 +183,41 @@ def serving_bench(n_req, planes, max_steps, plain=True):
     return out
 
 
+def transport_bench():
+    """The paper's two experiments on the hot path: the bulk shear-wave
+    viscosity of the 128^3 periodic box at sigma = 8 for each packing fraction,
+    with and without the SMDB cross-over term (5000 steps, amplitude read every
+    10), and the effective viscosity of 16x16xH slits at sigma = 8 for
+    eta = 0.11 and 0.32 (run to steady state)."""
+    from paper_1304_7880_amd import transport
+    from paper_1304_7880_amd.workloads import BULK_128, BULK_ETAS
+    w = BULK_128
+    bulk = []
+    for eta in BULK_ETAS:
+        row = {"eta": eta}
+        for smdb in (True, False):
+            r = transport.shear_wave_viscosity(eta, sigma=w.sigma, n=w.nz, steps=w.steps, every=10, tau=w.tau,
+                                               amp=w.shear_amp, smdb=smdb)
+            key = "smdb" if smdb else "dsb"
+            row[f"nu_{key}"] = round(r.nu, 6)
+            row[f"seconds_{key}"] = round(r.seconds, 2)
+            row[f"mlups_{key}"] = round(w.N * w.steps / r.seconds / 1e6, 1)
+        bulk.append(row)
+        print(json.dumps({"bulk_row": row}), file=sys.stderr, flush=True)
+    slits = []
+    for eta in (0.11, 0.32):
+        for H in (16, 32, 64, 128, 200):
+            r = transport.slit_effective_viscosity(H, eta, sigma=8.0, g=1e-6, nxy=16, tau=1.0, tol=1e-8,
+                                                   max_steps=400000)
+            row = {"eta": eta, "H": H, "nu_eff": round(r.nu_eff, 6), "steps": r.steps, "converged": r.converged}
+            slits.append(row)
+            print(json.dumps({"slit_row": row}), file=sys.stderr, flush=True)
+    return {"metric": "kinematic viscosity (shear-wave decay; slit nu_eff = g H^2 / (12 u_pore))",
+            "unit": "lattice units", "dtype": "fp32", "data": "synthetic",
+            "config": {"workload": f"{w.name}, 5000 steps; slits 16x16xH, sigma=8, tau=1, g_x=1e-6"},
+            "bulk": bulk, "slit": slits}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +233,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
                          "calibrating HBM byte counters under a profiler)")
+    ap.add_argument("--transport", action="store_true",
+                    help="run the viscosity experiments instead (bulk shear wave and slit widths); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the WDLB step on a single MI355X "
@@ -213,6 +250,9 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.transport:
+        print(json.dumps(transport_bench()), flush=True)
+        return
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
