@@ -43,3 +43,15 @@ def test_shear_fixture_matches_workload_and_symmetry():
     A = float(ux @ s / (s @ s))
     assert 0 < A < w.shear_amp
     assert np.abs(ux - A * s).max() < 1e-9 * A
+
+
+def test_slab64_fixture_matches_workload_and_mass():
+    from paper_1304_7880_amd.workloads import SLAB_64, initial_fields
+    ref = _golden("slab64_20000.json")
+    w = SLAB_64
+    assert (ref["nx"], ref["ny"], ref["nz"], ref["sigma"], ref["eta"], ref["tau"], ref["steps"]) == \
+        (w.nx, w.ny, w.nz, w.sigma, w.eta, w.tau, w.steps)
+    n, _ = initial_fields(w)
+    # the column started from the plane means of the seeded density: same mass
+    assert abs(np.sum(ref["n_z"]) * w.nx * w.ny - n.sum()) < 1e-10 * n.sum()
+    assert ref["j_pore"] > 0

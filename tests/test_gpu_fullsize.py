@@ -74,3 +74,29 @@ def test_bulk_shear_wave_full_size():
     _say(f"  u_x(z) rel {e_u:.3e}  n(z) rel {e_n:.3e}")
     assert e_u < 1e-5
     assert e_n < 1e-5
+
+
+def test_slab64_full_length_against_column_oracle():
+    """The benchmark slit (64^3, sigma = 6, seeded +-1 % density noise) after
+    its full 20000 steps: the noise has decayed over ~17 viscous times and the
+    flow is that of the x,y-homogeneous slit started from the plane means of
+    the same density (column oracle).  Bar: 1e-5 on u_x(z) and the flux."""
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import SLAB_64
+    ref = _golden("slab64_20000.json")
+    w = SLAB_64
+    _say(f"slab {w.name} fp32 {ref['steps']} steps")
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, True, "fp32", w.sigma, w.eta, w.tau, w.g)
+    n, u = initial_fields(w)
+    ctx.init_fields(n, u)
+    ctx.step(ref["steps"])
+    ctx.sync()
+    n_g, ux_g = ctx.read_profiles()
+    J_g, _, _ = ctx.read_flux()
+    ctx.destroy()
+    ux_o, J_o = np.array(ref["ux_z"]), ref["j_pore"]
+    e_u = float(np.abs(ux_g - ux_o).max() / np.abs(ux_o).max())
+    e_J = abs(J_g - J_o) / abs(J_o)
+    _say(f"  u_x(z) rel {e_u:.3e}  J rel {e_J:.3e}")
+    assert e_u < 1e-5
+    assert e_J < 1e-5
