@@ -233,7 +233,7 @@ def main():
                     help="requests of the serving trace replayed through the batched server and the plain loop "
                          "(0: skip)")
     ap.add_argument("--serving-planes", type=int, default=4096, help="z-planes of the serving lattice")
-    ap.add_argument("--serving-max-steps", type=int, default=200000)
+    ap.add_argument("--serving-max-steps", type=int, default=60000)
     ap.add_argument("--serving-no-plain", action="store_true", help="batched server only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "

@@ -184,6 +184,13 @@ const char *wdlb_kernel_name(int32_t kernel);
 wdlb_status wdlb_set_tile(wdlb_ctx *ctx, int32_t variant);
 wdlb_status wdlb_get_tile(wdlb_ctx *ctx, int32_t *variant, int32_t *specialised);
 
+/* wdlb_step replays pairs of steps as HIP graphs (captured on first use on
+ * a private stream, launched on the context's stream) unless kernel timing
+ * is on or the mode is WDLB_BF16_NEQ; the result is the same as stepping
+ * launch by launch.  wdlb_set_graphs(ctx, 0) turns replay off (1: on, the
+ * default). */
+wdlb_status wdlb_set_graphs(wdlb_ctx *ctx, int32_t enable);
+
 /* Message of the last failed call on this context ("" if none).  The
  * pointer stays valid until the next call on the context. */
 const char *wdlb_last_error(const wdlb_ctx *ctx);

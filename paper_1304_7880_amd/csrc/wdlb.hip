@@ -59,6 +59,12 @@ struct wdlb_ctx {
     int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
     int spec_b2;       // 2 sigma of the specialised density kernel in use, 0 = generic
     int cur;
+    // HIP graphs of two steps (one per starting parity), replayed by
+    // wdlb_step; captured on a private stream, launched on the caller's
+    bool graphs = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_nz_run = -1;
     int nz_run;        // planes the step kernels process (nz; fewer in a partly filled stacked lattice)
     int64_t step;
     bool inited;
@@ -370,8 +376,18 @@ wdlb_status upload_tables(wdlb_ctx *c)
     return WDLB_OK;
 }
 
+void drop_graphs(wdlb_ctx *c)
+{
+    for (auto &e : c->gexec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+}
+
 wdlb_status tables(wdlb_ctx *c)
 {
+    drop_graphs(c);  // launch parameters may change
     if (c->prec == WDLB_FP64) return upload_tables<double>(c);
     return upload_tables<float>(c);
 }
@@ -775,6 +791,49 @@ wdlb_status wdlb_set_params(wdlb_ctx *c, const wdlb_params *params)
     return tables(c);
 }
 
+// the two-step graph for the current parity, captured on first use (on the
+// private stream: the caller's may be the null stream, which cannot be
+// captured).  *ex stays null if capture is not possible; the caller then
+// steps eagerly.
+static wdlb_status step_graph(wdlb_ctx *c, hipGraphExec_t *ex)
+{
+    if (c->graph_nz_run != c->nz_run) {
+        drop_graphs(c);
+        c->graph_nz_run = c->nz_run;
+    }
+    const int par = c->cur;
+    if (!c->gexec[par]) {
+        if (!c->cap && hipStreamCreate(&c->cap) != hipSuccess) {
+            c->graphs = false;
+            return WDLB_OK;
+        }
+        hipStream_t keep = c->stream;
+        c->stream = c->cap;
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+        wdlb_status st = WDLB_OK;
+        if (ok) {
+            st = pass<false>(c);
+            c->cur ^= 1;
+            if (st == WDLB_OK) st = pass<false>(c);
+            c->cur ^= 1;
+            ok = hipStreamEndCapture(c->cap, &graph) == hipSuccess && st == WDLB_OK && graph != nullptr;
+        }
+        c->stream = keep;
+        hipGraphExec_t e = nullptr;
+        if (ok) ok = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (!ok) {
+            c->graphs = false;  // step eagerly from now on
+            return WDLB_OK;
+        }
+        c->gexec[par] = e;
+    }
+    *ex = c->gexec[par];
+    return WDLB_OK;
+}
+
 static wdlb_status do_init(wdlb_ctx *c, int uniform, const double u0[3], const double *h_n, const double *h_u)
 {
     const Geom g = c->g;
@@ -845,6 +904,19 @@ wdlb_status wdlb_step(wdlb_ctx *c, int64_t nsteps)
     if (!c) return WDLB_E_INVAL;
     if (nsteps < 0) return fail(c, WDLB_E_INVAL, "negative step count");
     if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
+    // pairs of steps by graph replay (not while kernels are timed, and not
+    // in the BF16 mode, whose rounding dither is keyed by the step number)
+    if (c->graphs && c->prof == 0 && c->prec != WDLB_BF16_NEQ) {
+        while (nsteps >= 2) {
+            hipGraphExec_t ex = nullptr;
+            wdlb_status st = step_graph(c, &ex);
+            if (st != WDLB_OK) return st;
+            if (!ex) break;  // capture not available: step eagerly
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+            c->step += 2;
+            nsteps -= 2;
+        }
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
         wdlb_status st = pass<false>(c);
         if (st != WDLB_OK) return st;
@@ -1081,10 +1153,21 @@ const char *wdlb_kernel_name(int32_t kernel) { return (kernel >= 0 && kernel < W
 
 const char *wdlb_last_error(const wdlb_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+wdlb_status wdlb_set_graphs(wdlb_ctx *c, int32_t enable)
+{
+    if (!c) return WDLB_E_INVAL;
+    c->graphs = enable != 0;
+    if (!c->graphs) drop_graphs(c);
+    return WDLB_OK;
+}
+
 void wdlb_destroy(wdlb_ctx *c)
 {
     if (!c) return;
     prof_flush(c);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     for (auto e : c->ev_free) (void)hipEventDestroy(e);
     delete c;
 }

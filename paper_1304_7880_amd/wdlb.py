@@ -31,7 +31,7 @@ SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_set_params", "wdlb_init_u
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
            "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
-           "wdlb_get_tile", "wdlb_last_error", "wdlb_destroy",
+           "wdlb_get_tile", "wdlb_set_graphs", "wdlb_last_error", "wdlb_destroy",
            "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
            "wdlb_server_drain", "wdlb_server_stats_get", "wdlb_server_last_error", "wdlb_server_destroy"]
 
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
     L.wdlb_kernel_name.restype = C.c_char_p
     L.wdlb_set_tile.argtypes = [vp, C.c_int32]
     L.wdlb_get_tile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.wdlb_set_graphs.argtypes = [vp, C.c_int32]
     L.wdlb_last_error.argtypes = [vp]
     L.wdlb_last_error.restype = C.c_char_p
     L.wdlb_destroy.argtypes = [vp]
@@ -286,6 +287,10 @@ class Context:
         v, sp = C.c_int32(), C.c_int32()
         self._chk(self._L.wdlb_get_tile(self.h, C.byref(v), C.byref(sp)), "get_tile")
         return v.value, bool(sp.value)
+
+    def set_graphs(self, enable=True):
+        """Replay pairs of steps as HIP graphs (default) or launch each kernel."""
+        self._chk(self._L.wdlb_set_graphs(self.h, int(bool(enable))), "set_graphs")
 
     def get_step(self):
         s = C.c_int64()
