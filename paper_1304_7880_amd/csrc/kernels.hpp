@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     const D dx = D(0.5) * Fx * inv, dy = D(0.5) * Fy * inv, dz = D(0.5) * Fz * inv;  // u* - u
     const D sx = D(2) * ux + dx, sy = D(2) * uy + dy, sz = D(2) * uz + dz;          // u + u*
     const D dsum = dx * sx + dy * sy + dz * sz;
-    D hv[Q];
+    R hv[Q];  // BF16 mode: h* kept for the closure
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         const D w = wgt<D>(a);
@@ -1182,7 +1182,9 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
         const D cd = D(CX[a]) * dx + D(CY[a]) * dy + D(CZ[a]) * dz;
         const D cs = D(CX[a]) * sx + D(CY[a]) * sy + D(CZ[a]) * sz;
         const D deq = w * rho * (-D(3) * cd - D(4.5) * cd * cs + D(1.5) * dsum);
-        hv[a] = keep * fneq + deq + ks * (guo + sa);
+        const R hva = R(keep * fneq + deq + ks * (guo + sa));
+        if constexpr (std::is_same<HS, bf16>::value) hv[a] = hva;  // rounded and closed below
+        else sth<R, HS>(h_out, a, N, i, hva);
     }
     if constexpr (std::is_same<HS, bf16>::value) {
         // round the others stochastically (dither from a counter-based
@@ -1211,9 +1213,6 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
         sth<R, HS>(h_out, 3, N, i, R(h3));
         sth<R, HS>(h_out, 5, N, i, R(h5));
         sth<R, HS>(h_out, 0, N, i, R(-(m + h1 + h3 + h5)));
-    } else {
-#pragma unroll
-        for (int a = 0; a < Q; ++a) sth<R, HS>(h_out, a, N, i, R(hv[a]));
     }
     ru_out[i] = V4<R>{R(rho), R(ux + dx), R(uy + dy), R(uz + dz)};
 }
