@@ -132,6 +132,7 @@ def serving_bench(n_req, planes, max_steps, plain=True):
     res_b = [srv.poll(i, H=r.H) for i, r in zip(ids, reqs)]
     st = srv.stats()
     srv.destroy()
+    print(f"serving: batched server done ({n_req} requests)", file=sys.stderr, flush=True)
     lat_b = [res.t_done - res.t_submit for res, _ in res_b]
     span_b = max(res.t_done for res, _ in res_b) - min(res.t_submit for res, _ in res_b)
     ok_b = [res.status == wdlb.OK for res, _ in res_b]
@@ -173,6 +174,8 @@ def serving_bench(n_req, planes, max_steps, plain=True):
         ctx.destroy()
         t_last = time.perf_counter() - t0
         lat_p.append(t_last - r.arrival_s)
+        if len(lat_p) % 32 == 0:
+            print(f"serving: plain loop {len(lat_p)}/{n_req}", file=sys.stderr, flush=True)
         same = same and status == rb.status and steps == rb.steps and (status != wdlb.OK or J == rb.j_pore)
     span_p = t_last - reqs[0].arrival_s
     out["plain"] = {"solves_per_s": round(n_req / span_p, 3), "makespan_s": round(span_p, 3),
