@@ -1010,6 +1010,36 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
 // every LDS offset is an immediate and every weight a literal.  Offsets are
 // taken from the corner of each lane's stencil window (non-negative).
 // ---------------------------------------------------------------------------
+// Quads with a = 0 or b = 0 have only two distinct mirror images (one when
+// both are 0), and their x- or y-odd Hadamard outputs are exact zeros whose
+// weights are zero as well.  The compiled kernels sum the distinct images
+// once, with the weights scaled by 2 (or 4): doubling is exact, so the
+// result is bit-identical to the four-image path of the table-driven
+// kernels, which repeats each image (weight 1/2 or 1/4).
+template <typename R>
+__device__ __forceinline__ void mf_quad_pair(R g0, R r0, R g1, R r1, R p_odd, R pz, R &f_odd, R &fz)
+{
+    R d, s;
+    {
+#pragma clang fp contract(off)
+        const R G0 = g0 * r0, G1 = g1 * r1;
+        d = G0 - G1;
+        s = G0 + G1;
+    }
+    f_odd += p_odd * d;
+    fz += pz * s;
+}
+
+template <typename R>
+__device__ __forceinline__ void sh_w(R g, const V4<R> &sv, const V4<R> &c0, R &wx, R &wy, R &wz)
+{
+#pragma clang fp contract(off)
+    const R G = g * sv.x;
+    wx = G * (sv.y - c0.y);
+    wy = G * (sv.z - c0.z);
+    wz = G * (sv.w - c0.w);
+}
+
 template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
 __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const R *__restrict__ rho_p,
                                                             const R *__restrict__ jx, const R *__restrict__ jy,
@@ -1039,10 +1069,25 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
             constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
             constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
                           gnb = (O + ((-b) >> 1)) * LXg;
-            const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
-            const R rm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
-                             pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
-            mf_quad<R>(gm, rm, R(Q.px), R(Q.py), R(Q.pz), fx, fy, fz);
+            if constexpr (a == 0 && b == 0) {
+                R G;
+                {
+#pragma clang fp contract(off)
+                    G = gc[hb + ga + gb] * pc[RC + RC * LX];
+                }
+                fz += R(4 * Q.pz) * G;
+            } else if constexpr (a == 0) {  // images (0, b) and (0, -b)
+                mf_quad_pair<R>(gc[hb + ga + gb], pc[RC + (RC + b) * LX], gc[hb + ga + gnb], pc[RC + (RC - b) * LX],
+                                R(2 * Q.py), R(2 * Q.pz), fy, fz);
+            } else if constexpr (b == 0) {  // images (a, 0) and (-a, 0)
+                mf_quad_pair<R>(gc[hb + ga + gb], pc[(RC + a) + RC * LX], gc[hb + gna + gb], pc[(RC - a) + RC * LX],
+                                R(2 * Q.px), R(2 * Q.pz), fx, fz);
+            } else {
+                const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+                const R rm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                                 pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+                mf_quad<R>(gm, rm, R(Q.px), R(Q.py), R(Q.pz), fx, fy, fz);
+            }
         });
         pin(fx);
         pin(fy);
@@ -1083,11 +1128,70 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
             constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
             constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
                           gnb = (O + ((-b) >> 1)) * LXg;
-            const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
-            const V4<R> sm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
-                                 pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
-            sh_quad<R>(gm, sm, c0, R(Q.px), R(Q.py), R(Q.pz), R(Q.qxx), R(Q.qyy), R(Q.qzz), R(Q.qxy), R(Q.qxz),
-                       R(Q.qyz), acc);
+            if constexpr (a == 0 && b == 0) {
+                // one image: only the z-even outputs, 4 W, remain
+                R wx, wy, wz;
+                sh_w<R>(gc[hb + ga + gb], pc[RC + RC * LX], c0, wx, wy, wz);
+                acc[2] += R(4 * Q.qzz) * wz;
+                acc[5] += R(4 * Q.pz) * wz;
+                acc[7] += R(4 * Q.pz) * wx;
+                acc[8] += R(4 * Q.pz) * wy;
+            } else if constexpr (a == 0) {
+                // images (0, b), (0, -b): the x-odd outputs vanish, the others
+                // are twice the sum (even) or difference (y-odd) of the two
+                R w0x, w0y, w0z, w2x, w2y, w2z, x0h, xYh, y0h, yYh, z0h, zYh;
+                sh_w<R>(gc[hb + ga + gb], pc[RC + (RC + b) * LX], c0, w0x, w0y, w0z);
+                sh_w<R>(gc[hb + ga + gnb], pc[RC + (RC - b) * LX], c0, w2x, w2y, w2z);
+                {
+#pragma clang fp contract(off)
+                    x0h = w0x + w2x;
+                    xYh = w0x - w2x;
+                    y0h = w0y + w2y;
+                    yYh = w0y - w2y;
+                    z0h = w0z + w2z;
+                    zYh = w0z - w2z;
+                }
+                acc[1] += R(2 * Q.qyy) * y0h;
+                acc[1] += R(2 * Q.qyz) * zYh;
+                acc[2] += R(2 * Q.qyz) * yYh;
+                acc[2] += R(2 * Q.qzz) * z0h;
+                acc[4] += R(2 * Q.py) * yYh;
+                acc[5] += R(2 * Q.pz) * z0h;
+                acc[6] += R(2 * Q.py) * xYh;
+                acc[7] += R(2 * Q.pz) * x0h;
+                acc[8] += R(2 * Q.pz) * y0h;
+                acc[8] += R(2 * Q.py) * zYh;
+            } else if constexpr (b == 0) {
+                // images (a, 0), (-a, 0): the y-odd outputs vanish
+                R w0x, w0y, w0z, w1x, w1y, w1z, x0h, xXh, y0h, yXh, z0h, zXh;
+                sh_w<R>(gc[hb + ga + gb], pc[(RC + a) + RC * LX], c0, w0x, w0y, w0z);
+                sh_w<R>(gc[hb + gna + gb], pc[(RC - a) + RC * LX], c0, w1x, w1y, w1z);
+                {
+#pragma clang fp contract(off)
+                    x0h = w0x + w1x;
+                    xXh = w0x - w1x;
+                    y0h = w0y + w1y;
+                    yXh = w0y - w1y;
+                    z0h = w0z + w1z;
+                    zXh = w0z - w1z;
+                }
+                acc[0] += R(2 * Q.qxx) * x0h;
+                acc[0] += R(2 * Q.qxz) * zXh;
+                acc[2] += R(2 * Q.qxz) * xXh;
+                acc[2] += R(2 * Q.qzz) * z0h;
+                acc[3] += R(2 * Q.px) * xXh;
+                acc[5] += R(2 * Q.pz) * z0h;
+                acc[6] += R(2 * Q.px) * yXh;
+                acc[7] += R(2 * Q.pz) * x0h;
+                acc[7] += R(2 * Q.px) * zXh;
+                acc[8] += R(2 * Q.pz) * y0h;
+            } else {
+                const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+                const V4<R> sm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                                     pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+                sh_quad<R>(gm, sm, c0, R(Q.px), R(Q.py), R(Q.pz), R(Q.qxx), R(Q.qyy), R(Q.qzz), R(Q.qxy),
+                           R(Q.qxz), R(Q.qyz), acc);
+            }
         });
 #pragma unroll
         for (int k = 0; k < 9; ++k) pin(acc[k]);
