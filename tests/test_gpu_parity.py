@@ -47,6 +47,8 @@ CASES = [
     ("walled 12x9x21 sigma=8", (12, 9, 21), True, 8.0, 0.3, 0.9, (1e-4, 0, 0), 2),
     # 16 wide in x: the narrow 16x16x2 tiles (compiled for sigma = 4 in fp32)
     ("walled 16x16x14 sigma=4 (narrow tiles)", (16, 16, 14), True, 4.0, 0.3, 1.0, (2e-5, 0, 0), 3),
+    # the largest compiled shell (reach 11) against the oracle's fields
+    ("walled 22x21x26 sigma=10", (22, 21, 26), True, 10.0, 0.3, 0.9, (1e-4, 0, 0), 2),
 ]
 
 
