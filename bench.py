@@ -186,17 +186,19 @@ def serving_bench(n_req, planes, max_steps, plain=True):
     return out
 
 
-def transport_bench():
-    """The paper's two experiments on the hot path: the bulk shear-wave
-    viscosity of the 128^3 periodic box at sigma = 8 for each packing fraction,
-    with and without the SMDB cross-over term (5000 steps, amplitude read every
-    10), and the effective viscosity of 16x16xH slits at sigma = 8 for
-    eta = 0.11 and 0.32 (run to steady state)."""
+def transport_bench(parts=("bulk", "sound", "slit")):
+    """Transport experiments on the hot path, each part optional: the bulk
+    shear-wave viscosity of the 128^3 periodic box at sigma = 8 for each
+    packing fraction, with and without the SMDB cross-over term (5000 steps,
+    amplitude read every 10); the sound speed and longitudinal viscosity of a
+    standing density wave in the same box (2000 steps, read every 2); and the
+    effective viscosity of 16x16xH slits at sigma = 8 for eta = 0.11 and 0.32
+    (run to steady state)."""
     from paper_1304_7880_amd import transport, wdlb
     from paper_1304_7880_amd.workloads import BULK_128, BULK_ETAS
     w = BULK_128
     bulk = []
-    for eta in BULK_ETAS:
+    for eta in (BULK_ETAS if "bulk" in parts else ()):
         row = {"eta": eta}
         for smdb in (True, False):
             key = "smdb" if smdb else "dsb"
@@ -212,18 +214,37 @@ def transport_bench():
             row[f"mlups_{key}"] = round(w.N * w.steps / r.seconds / 1e6, 1)
         bulk.append(row)
         print(json.dumps({"bulk_row": row}), file=sys.stderr, flush=True)
+    # longitudinal waves in the same box: c^2 against Carnahan-Starling, and the
+    # bulk viscosity nu_L - (4/3) nu_shear (both with the SMDB term)
+    sound = []
+    for eta in (BULK_ETAS if "sound" in parts else ()):
+        row_b = next((b for b in bulk if b["eta"] == eta), {})
+        row = {"eta": eta, "c2_cs": round(transport.carnahan_starling_c2(eta), 6)}
+        try:
+            r = transport.longitudinal_wave(eta, sigma=w.sigma, n=w.nz, steps=2000, every=2, tau=w.tau, eps=1e-3)
+        except wdlb.WdlbError as e:
+            row["status"] = str(e).split(":")[0]
+            sound.append(row)
+            continue
+        row.update(c2=round(r.c2, 6), nu_long=round(r.nu_long, 6), seconds=round(r.seconds, 2))
+        if row_b.get("nu_smdb") is not None:
+            row["nu_bulk"] = round(r.nu_long - 4.0 / 3.0 * row_b["nu_smdb"], 6)
+        sound.append(row)
+        print(json.dumps({"sound_row": row}), file=sys.stderr, flush=True)
     slits = []
-    for eta in (0.11, 0.32):
+    for eta in ((0.11, 0.32) if "slit" in parts else ()):
         for H in (16, 32, 64, 128, 200):
             r = transport.slit_effective_viscosity(H, eta, sigma=8.0, g=1e-6, nxy=16, tau=1.0, tol=1e-8,
                                                    max_steps=400000)
             row = {"eta": eta, "H": H, "nu_eff": round(r.nu_eff, 6), "steps": r.steps, "converged": r.converged}
             slits.append(row)
             print(json.dumps({"slit_row": row}), file=sys.stderr, flush=True)
-    return {"metric": "kinematic viscosity (shear-wave decay; slit nu_eff = g H^2 / (12 u_pore))",
+    return {"metric": "kinematic viscosity (shear-wave decay; slit nu_eff = g H^2 / (12 u_pore)) and squared "
+                      "sound speed (density-wave oscillation)",
             "unit": "lattice units", "dtype": "fp32", "data": "synthetic",
-            "config": {"workload": f"{w.name}, 5000 steps; slits 16x16xH, sigma=8, tau=1, g_x=1e-6"},
-            "bulk": bulk, "slit": slits}
+            "config": {"workload": f"{w.name}, shear 5000 steps, sound 2000 steps; slits 16x16xH, sigma=8, tau=1, "
+                                   "g_x=1e-6"},
+            "bulk": bulk, "sound": sound, "slit": slits}
 
 
 def main():
@@ -241,8 +262,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
                          "calibrating HBM byte counters under a profiler)")
-    ap.add_argument("--transport", action="store_true",
-                    help="run the viscosity experiments instead (bulk shear wave and slit widths); one JSON line")
+    ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
+                    help="run the transport experiments instead (comma list of bulk, sound, slit; default all); "
+                         "one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the WDLB step on a single MI355X "
@@ -259,7 +281,10 @@ def main():
         __graft_entry__.build()
     torch.cuda.set_device(0)
     if args.transport:
-        print(json.dumps(transport_bench()), flush=True)
+        parts = tuple(x for x in args.transport.split(",") if x)
+        if not parts or set(parts) - {"bulk", "sound", "slit"}:
+            sys.exit("--transport takes a comma list of bulk, sound, slit")
+        print(json.dumps(transport_bench(parts)), flush=True)
         return
     stream = torch.cuda.current_stream()
     if args.copy_calibration:

@@ -1,8 +1,10 @@
 """Transport coefficients measured on the GPU (paper_1304_7880_amd.transport)
 against the same quantities from the FP64 column oracle, fitted here
-independently: the shear-wave viscosity (with and without the SMDB term) and
-the effective viscosity of a slit pore.  Bars: 1e-4 relative (FP32 fields
-agree to ~1e-6; the fit amplifies little)."""
+independently: the shear-wave viscosity (with and without the SMDB term),
+the effective viscosity of a slit pore, and the sound speed and longitudinal
+viscosity of a standing density wave.  Bars: 1e-4 relative for the FP32
+viscosities (FP32 fields agree to ~1e-6; the fit amplifies little); the
+sound wave's bars are stated with its test."""
 import math
 import sys
 
@@ -76,3 +78,52 @@ def test_slit_effective_viscosity_matches_column_oracle():
     nu_o = g * H * H / (12.0 * upore)
     _say(f"  H={H}: steps {r.steps}, nu_eff gpu {r.nu_eff:.6f} oracle {nu_o:.6f}")
     assert abs(r.nu_eff - nu_o) < 1e-4 * nu_o
+
+
+def _lp_fit(ts, B):
+    """Two-term linear recurrence B[k+1] = a1 B[k] + a2 B[k-1] of a sampled
+    damped cosine -> (omega, Gamma)."""
+    A = np.stack([B[1:-1], B[:-2]], axis=1)
+    a1, a2 = np.linalg.lstsq(A, B[2:], rcond=None)[0]
+    r = math.sqrt(-a2)
+    dt = ts[1] - ts[0]
+    return math.acos(a1 / (2 * r)) / dt, -math.log(r) / dt
+
+
+@pytest.mark.parametrize("prec,tol_amp,tol_c2,tol_nu", [("fp64", 1e-9, 1e-9, 1e-8), ("fp32", 2e-4, 2e-5, 1e-3)])
+def test_sound_wave_matches_column_oracle(prec, tol_amp, tol_c2, tol_nu):
+    """Density wave eps = 1e-3 in a periodic 8x8x64 box at sigma = 4, eta =
+    0.25: the amplitude B(t) read every 2 steps equals the column oracle's
+    (relative to B(0)), and so do the fitted c^2 and nu_L.  FP32 stores rho
+    with a 6e-8 relative rounding, 6e-5 of the 1e-3 perturbation; the decay
+    rate is the small part of the fit and takes the larger bar."""
+    from paper_1304_7880_amd import transport
+    n, sigma, eta, tau, steps, every, eps, skip = 64, 4.0, 0.25, 1.0, 360, 2, 1e-3, 60
+    r = transport.longitudinal_wave(eta, sigma=sigma, n=n, nxy=8, steps=steps, every=every, tau=tau, eps=eps,
+                                    precision=prec, skip=skip, floor=0.0)
+    n0 = packing_to_density(eta, sigma)
+    z = np.arange(n, dtype=np.float64)
+    s = np.sin(2 * math.pi * z / n)
+    col = Column(n, sigma=sigma, tau=tau, walls=False)
+    col.init(n0 * (1 + eps * s), np.zeros((3, n)))
+    ts, B = [], []
+    for t in range(0, steps + 1, every):
+        rho = col.reduce()[0]
+        ts.append(t)
+        B.append(2.0 / n * float((rho / n0 - 1) @ s))
+        if t < steps:
+            col.step(every)
+    ts, B = np.array(ts, float), np.array(B)
+    assert np.array_equal(ts, r.times)
+    err = np.abs(r.amp - B).max() / abs(B[0])
+    sel = ts >= skip
+    om, ga = _lp_fit(ts[sel], B[sel])
+    q = 2 * math.pi / n
+    c2_o, nu_o = (om * om + ga * ga) / q ** 2, 2 * ga / q ** 2
+    _say(f"  {prec}: amp err {err:.2e}; c2 gpu {r.c2:.8f} oracle {c2_o:.8f}; nu_L gpu {r.nu_long:.6f} "
+         f"oracle {nu_o:.6f}")
+    assert err < tol_amp
+    assert abs(r.c2 - c2_o) < tol_c2 * c2_o
+    assert abs(r.nu_long - nu_o) < tol_nu * nu_o
+    # the Carnahan-Starling sound speed, within the lattice-shell factor at sigma = 4
+    assert abs(r.c2 / transport.carnahan_starling_c2(eta) - 1) < 0.02

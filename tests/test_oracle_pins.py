@@ -227,6 +227,70 @@ def test_shear_wave_decay_rate():
 
 
 # --------------------------------------------------------------------------
+# Longitudinal (sound) wave (Sec. 4: small-gradient theory; the pressure of
+# the mean-field force is the Carnahan-Starling one, the bulk viscosity comes
+# from F^v alone, the SMDB A-field is traceless).  For n = n0 (1 + eps sin qz)
+# at rest, the standing wave rho ~ exp(-Gamma t) cos(omega t) has
+#   c^2 q^2 = omega^2 + Gamma^2 = kT q^2 + n0 kT sigma^2 wS q S_F,
+#     S_F = g0 sum_e kz sin(q e_z) + eta g0' B_q sum_e kz c_e sin(q e_z / 2)
+#   (the static linear response above turned into a restoring force), and
+#   nu_L q^2 = 2 Gamma = 2 cs^2 (tau - 1/2) q^2          (BGK: 4/3 shear + 2/3 bulk)
+#            + 2 sigma^2 sqrt(kT/pi) wS g0 n0 sum_e kz^2 (1 - cos q e_z)   (F^v)
+#            + (4/3) (tau - 1/2) (kT/5) sigma^2 n0 wS g0 q K_A            (traceless A)
+# to leading order in the time step (omega dt ~ 0.06 here).  Fitted with a
+# damped cosine by nonlinear least squares.
+# --------------------------------------------------------------------------
+def _sound_wave(sigma, eta, tau, L, smdb, steps, skip, eps=1e-6):
+    from scipy.optimize import curve_fit
+    col = Column(L, sigma, tau, walls=False, smdb=smdb)
+    n0 = packing_to_density(eta, sigma)
+    z = np.arange(L)
+    q = 2 * math.pi / L
+    col.init(n0 * (1 + eps * np.sin(q * z)), np.zeros((3, L)))
+    ts, amps = [], []
+    for t in range(steps):
+        if t >= skip:
+            rho, _, _, _ = col.fields()
+            ts.append(t)
+            amps.append(2.0 / L * ((rho / n0 - 1) * np.sin(q * z)).sum() / eps)
+        col.step(1)
+    ts, amps = np.array(ts, float), np.array(amps)
+
+    def model(t, b, gam, om, ph):
+        return b * np.exp(-gam * t) * np.cos(om * t + ph)
+
+    (b, gam, om, ph), _ = curve_fit(model, ts, amps, p0=(1.0, 1e-3, 0.05, 0.0))
+    return om, gam, n0, q
+
+
+def test_sound_wave_speed_and_attenuation():
+    sigma, eta, tau, L, steps, skip = 4, 0.1, 1.0, 64, 700, 60
+    om, gam, n0, q = _sound_wave(sigma, eta, tau, L, True, steps, skip)
+    om_off, gam_off, _, _ = _sound_wave(sigma, eta, tau, L, False, steps, skip)
+    S = ref.shell(sigma).astype(float)
+    B = ref.ball(sigma).astype(float)
+    k = S / np.linalg.norm(S, axis=1)[:, None]
+    wS = 4 * math.pi / len(S)
+    g0, dg0 = g_cs(eta), dg_cs(eta)
+    Bq = np.cos(q * B[:, 2]).mean()
+    ce = np.where(S[:, 2] % 2 == 0, 1.0, math.cos(q / 2))
+    SF = g0 * (k[:, 2] * np.sin(q * S[:, 2])).sum() + eta * dg0 * Bq * (k[:, 2] * ce * np.sin(q * S[:, 2] / 2)).sum()
+    c2q2 = KT * q * q + n0 * KT * sigma ** 2 * wS * q * SF
+    lam = tau - 0.5
+    r_v = 2 * sigma ** 2 * math.sqrt(KT / math.pi) * wS * g0 * n0 * (k[:, 2] ** 2 * (1 - np.cos(q * S[:, 2]))).sum()
+    r_A = lam * (KT / 5) * sigma ** 2 * n0 * wS * g0 * q * (k[:, 2] * np.sin(q * S[:, 2])).sum()
+    for o, gm, a in ((om, gam, 4.0 / 3.0), (om_off, gam_off, 0.0)):
+        assert abs((o * o + gm * gm) / c2q2 - 1) < 3e-3
+        nuLq2 = 2 * KT * lam * q * q + r_v + a * r_A
+        assert abs(2 * gm / nuLq2 - 1) < 1e-2
+    # the traceless A-field adds 4/3 of its shear-wave rate to the longitudinal one
+    assert abs(2 * (gam - gam_off) / (4.0 / 3.0 * r_A) - 1) < 3e-2
+    # long waves: the Carnahan-Starling sound speed c^2 = kT d(n Z)/dn
+    c2_cs = KT * (1 + 4 * eta + 4 * eta ** 2 - 4 * eta ** 3 + eta ** 4) / (1 - eta) ** 4
+    assert abs(c2q2 / (q * q) / c2_cs - 1) < 2e-2
+
+
+# --------------------------------------------------------------------------
 # P12: 1-D column oracle == 3-D oracle on x,y-homogeneous states.
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("walls,sigma,eta,tau,g,steps", [
