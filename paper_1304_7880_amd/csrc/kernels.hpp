@@ -352,21 +352,43 @@ __device__ __forceinline__ void static_for(F &&f)
 __host__ __device__ constexpr size_t density_lds_bytes(int TX, int TY, int TZ, int rb, size_t rbytes)
 {
     return ((size_t)(TX + 2 * rb + 1) * (TY + 2 * rb + 1) * (TZ + 2 * rb + 1) + (size_t)(TX + 1) * (TY + 1) * (TZ + 1)) *
-           rbytes;
+               rbytes +
+           (size_t)(TZ + 1) * sizeof(int);  // fluid flags of the nbar planes
 }
 
 // rho over the tile, the ball reach and one extra node (from the padded
-// array: images and zeros beyond the walls are in place)
-template <typename R, int NT>
-__device__ __forceinline__ void density_fill(const TileCoord &tc, const Pad &p, int rb, int LX, int LY, int LZ,
-                                             const R *__restrict__ rho_p, R *win)
+// array: images and zeros beyond the walls are in place), and the fluid flag
+// of each of the TZ + 1 nbar planes (zfl).  The window is fetched in rounds
+// of 8 elements per lane, all 8 loads issued before the first is stored; a
+// load and its store take the same branch, so that the compiler does not
+// sink the load next to the store (one load latency per round).
+template <typename R, int NT, int TZ>
+__device__ __forceinline__ void density_fill(const Geom &g, const TileCoord &tc, const Pad &p, int rb, int LX, int LY,
+                                             int LZ, const R *__restrict__ rho_p, R *win, int *zfl)
 {
-    for (int e = threadIdx.x; e < LX * LY * LZ; e += NT) {
-        const int ix = e % LX, t = e / LX, iy = t % LY, iz = t / LY;
-        const int X = min(max(tc.x0 - rb + ix + p.P, 0), p.PX - 1);
-        const int Y = min(max(tc.y0 - rb + iy + p.P, 0), p.PY - 1);
-        const int Z = min(max(tc.z0 - rb + iz + p.P, 0), p.PZ - 1);
-        win[e] = rho_p[(long long)Z * p.PXY + (long long)Y * p.PX + X];
+    const int NE = LX * LY * LZ;
+    const int t0 = threadIdx.x;
+    // NE > NT (the window holds the tile and more), so every lane runs the first round
+    for (int e0 = t0; e0 < NE; e0 += 8 * NT) {
+        R v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            if (e < NE) {
+                const int ix = e % LX, t = e / LX, iy = t % LY, iz = t / LY;
+                const int X = min(max(tc.x0 - rb + ix + p.P, 0), p.PX - 1);
+                const int Y = min(max(tc.y0 - rb + iy + p.P, 0), p.PY - 1);
+                const int Z = min(max(tc.z0 - rb + iz + p.P, 0), p.PZ - 1);
+                v[u] = rho_p[(long long)Z * p.PXY + (long long)Y * p.PX + X];
+            }
+        }
+        // in the first round, behind the window loads: the plane flags
+        if (e0 == t0 && t0 <= TZ) zfl[t0] = !g.walls || zfluid(g, tc.z0 + t0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            if (e < NE) win[e] = v[u];
+        }
     }
 }
 
@@ -441,12 +463,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, c
     const int LX = TX + 2 * rb + 1, LY = TY + 2 * rb + 1, LZ = TZ + 2 * rb + 1, LXY = LX * LY;
     R *win = reinterpret_cast<R *>(lds_raw);
     R *nb = win + (size_t)LX * LY * LZ;
-    density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
+    int *zfl = reinterpret_cast<int *>(nb + MN);
+    density_fill<R, NT, TZ>(g, tc, p, rb, LX, LY, LZ, rho_p, win, zfl);
     __syncthreads();
     auto nbar_at = [&](int mx, int my, int mz) {
-        const int zz = tc.z0 + mz;
         R v = 0;
-        if (!g.walls || zfluid(g, zz)) {
+        if (zfl[mz]) {
             const R *c = win + mz * LXY + my * LX + mx;
             R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             int k = 0;
@@ -483,12 +505,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R
     const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
     R *win = reinterpret_cast<R *>(lds_raw);
     R *nb = win + (size_t)LX * LY * LZ;
-    density_fill<R, NT>(tc, p, rb, LX, LY, LZ, rho_p, win);
+    int *zfl = reinterpret_cast<int *>(nb + MN);
+    density_fill<R, NT, TZ>(g, tc, p, rb, LX, LY, LZ, rho_p, win, zfl);
     __syncthreads();
     auto nbar_at = [&](int mx, int my, int mz) __attribute__((always_inline)) {
-        const int zz = tc.z0 + mz;
         R v = 0;
-        if (!g.walls || zfluid(g, zz)) {
+        if (zfl[mz]) {
             const R *c = win + mz * LXY + my * LX + mx;  // corner of the lane's ball window
             R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             static_for<0, B::NB>([&](auto ki) __attribute__((always_inline)) {
@@ -561,14 +583,41 @@ struct GammaRing {
             goff[k] = Y * p.PX + X;
         }
     }
-    // slice t (plane z0 + floor(t/2), z-parity t & 1) into staging set S
-    template <int S>
-    __device__ __forceinline__ void fetch(const R *__restrict__ gam_p, const Pad &p, int z0, int t)
+    // slice t (plane z0 + floor(t/2), z-parity t & 1) into registers d
+    __device__ __forceinline__ void fetch_to(R (&d)[NG], const R *__restrict__ gam_p, const Pad &p, int z0, int t)
     {
         const int hz = t & 1;
         const long long zb = (long long)min(max(z0 + (t >> 1) + p.P, 0), p.PZ - 1) * p.PXY;
 #pragma unroll
-        for (int k = 0; k < NG; ++k) st[S][k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
+        for (int k = 0; k < NG; ++k) d[k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
+    }
+    // With GUARD the fetch takes the store's branch per element: unguarded,
+    // the compiler may sink a fetch into that branch, to the end of the step
+    // (where store() runs), and expose its whole latency there.  That costs
+    // a step with one step of prefetch (PD = 1); with PD = 2 it does not.
+    template <int S, bool GUARD>
+    __device__ __forceinline__ void fetch(const R *__restrict__ gam_p, const Pad &p, int z0, int t)
+    {
+        if constexpr (!GUARD) {
+            fetch_to(st[S], gam_p, p, z0, t);
+        } else {
+            const int hz = t & 1;
+            const long long zb = (long long)min(max(z0 + (t >> 1) + p.P, 0), p.PZ - 1) * p.PXY;
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+                if ((int)threadIdx.x + k * NT < LS)
+                    st[S][k] = gam_p[(long long)(gh[k] + 4 * hz) * p.NP + zb + goff[k]];
+        }
+    }
+    // Store without a branch: a lane past the end of the slice holds the
+    // slice's last element (its fetch offset was clamped) and writes it where
+    // the lane that owns it does.  Used once, before the step loop, where the
+    // branch of store() would let the compiler sink each fetch next to its
+    // store and serialise the loads of the whole fill.
+    __device__ __forceinline__ void store_all(const R (&d)[NG], R *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) win[slot * LS + min((int)threadIdx.x + k * NT, LS - 1)] = d[k];
     }
     template <int S>
     __device__ __forceinline__ void store(R *win, int slot)
@@ -623,15 +672,43 @@ struct PlaneRing {
             off[k] = Y * p.PX + X;
         }
     }
-    template <int S>
-    __device__ __forceinline__ void fetch(const V *__restrict__ src, const Pad &p, int pz)
+    __device__ __forceinline__ void fetch_to(R (&d)[NC][NR], const V *__restrict__ src, const Pad &p, int pz)
     {
         const long long zb = (long long)min(max(pz + p.P, 0), p.PZ - 1) * p.PXY;
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const V v = src[zb + off[k]];
 #pragma unroll
-            for (int m = 0; m < NC; ++m) st[S][m][k] = Comp<V>::get(v, m);
+            for (int m = 0; m < NC; ++m) d[m][k] = Comp<V>::get(v, m);
+        }
+    }
+    // GUARD as in GammaRing::fetch
+    template <int S, bool GUARD>
+    __device__ __forceinline__ void fetch(const V *__restrict__ src, const Pad &p, int pz)
+    {
+        if constexpr (!GUARD) {
+            fetch_to(st[S], src, p, pz);
+        } else {
+            const long long zb = (long long)min(max(pz + p.P, 0), p.PZ - 1) * p.PXY;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if ((int)threadIdx.x + k * NT < LP) {
+                    const V v = src[zb + off[k]];
+#pragma unroll
+                    for (int m = 0; m < NC; ++m) st[S][m][k] = Comp<V>::get(v, m);
+                }
+            }
+        }
+    }
+    // branch-free store of a whole plane, as GammaRing::store_all
+    __device__ __forceinline__ void store_all(const R (&d)[NC][NR], V *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            V v;
+#pragma unroll
+            for (int m = 0; m < NC; ++m) Comp<V>::set(v, m, d[m][k]);
+            win[slot * LP + min((int)threadIdx.x + k * NT, LP - 1)] = v;
         }
     }
     template <int S>
@@ -697,20 +774,25 @@ struct ShellRings {
             gr.setup(p, Rr, TX, TY, tc.x0, tc.y0);
             gcen = (tc.ly + o) * gr.LXg + (tc.lx + o);
         }
+        // the fill: the first TZ planes and 2 TZ - 1 slices, all fetched
+        // before any is stored (one load latency for the whole fill)
+        R pst[TZ][PlaneRing<R, V, NT, NR>::NC][NR];
+        R gst[GL ? 2 * TZ - 1 : 1][GL ? NG : 1];
 #pragma unroll
-        for (int k = 0; k < TZ; ++k) {
-            pr.template fetch<0>(src, p, z0 - Rr + k);
-            pr.template store<0>(win, k);
-        }
+        for (int k = 0; k < TZ; ++k) pr.fetch_to(pst[k], src, p, z0 - Rr + k);
         if constexpr (GL) {
-            for (int t = -Rr; t <= -Rr + 2 * TZ - 2; ++t) {
-                gr.template fetch<0>(gam_p, p, z0, t);
-                gr.template store<0>(gwin, (t + 64) % NSG);
-            }
+#pragma unroll
+            for (int j = 0; j < 2 * TZ - 1; ++j) gr.fetch_to(gst[j], gam_p, p, z0, j - Rr);
         }
         if constexpr (PD == 2) {  // what step -R stores at its end
-            pr.template fetch<0>(src, p, z0 + TZ - Rr);
-            if constexpr (GL) gr.template fetch<0>(gam_p, p, z0, 2 * TZ - 1 - Rr);
+            pr.template fetch<0, false>(src, p, z0 + TZ - Rr);
+            if constexpr (GL) gr.template fetch<0, false>(gam_p, p, z0, 2 * TZ - 1 - Rr);
+        }
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) pr.store_all(pst[k], win, k);
+        if constexpr (GL) {
+#pragma unroll
+            for (int j = 0; j < 2 * TZ - 1; ++j) gr.store_all(gst[j], gwin, (j - Rr + 64) % NSG);
         }
         __syncthreads();
     }
@@ -719,12 +801,12 @@ struct ShellRings {
     {
         if constexpr (PD == 2) {
             if (c + 1 < Rr) {
-                pr.template fetch<S ^ 1>(src, p, z0 + c + 1 + TZ);
-                if constexpr (GL) gr.template fetch<S ^ 1>(gam_p, p, z0, c + 2 * TZ);
+                pr.template fetch<S ^ 1, false>(src, p, z0 + c + 1 + TZ);
+                if constexpr (GL) gr.template fetch<S ^ 1, false>(gam_p, p, z0, c + 2 * TZ);
             }
         } else if (c < Rr) {
-            pr.template fetch<0>(src, p, z0 + c + TZ);
-            if constexpr (GL) gr.template fetch<0>(gam_p, p, z0, c + 2 * TZ - 1);
+            pr.template fetch<0, true>(src, p, z0 + c + TZ);
+            if constexpr (GL) gr.template fetch<0, true>(gam_p, p, z0, c + 2 * TZ - 1);
         }
     }
     template <int S>
