@@ -196,26 +196,47 @@ __device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int ti
 // ---------------------------------------------------------------------------
 typedef double D;
 
-template <typename R, typename HS>
-__device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h, int x,
-                                   int y, int z, int r, int a)
+// The neighbours a node pulls from, found once per node: the wrapped
+// coordinates x -+ 1, y -+ 1, z -+ 1 and whether the planes z - 1 and z + 1
+// are fluid (bbm, bbp: a population arriving from a non-fluid plane is
+// bounced back at the node itself).  With them every pull is straight-line
+// code, so the compiler can issue all 19 pairs of loads before it waits.
+struct PullNbr {
+    int xm, xp, ym, yp, zm, zp;
+    bool bbm, bbp;
+};
+
+__device__ __forceinline__ PullNbr pull_nbr(const Geom &g, int x, int y, int z)
 {
-    int sz = z - CZ[a];
-    bool bb = false;
-    if (CZ[a] != 0) {
-        if (g.walls) bb = !zfluid(g, sz);
-        else sz = wrap1(sz, g.nz);
-    }
-    int s, ha;
-    if (bb) {
-        s = r;
-        ha = OPP[a];
+    PullNbr n;
+    n.xm = wrap1(x - 1, g.nx);
+    n.xp = wrap1(x + 1, g.nx);
+    n.ym = wrap1(y - 1, g.ny);
+    n.yp = wrap1(y + 1, g.ny);
+    if (g.walls) {
+        n.zm = z - 1;
+        n.zp = z + 1;
+        n.bbm = !zfluid(g, z - 1);
+        n.bbp = !zfluid(g, z + 1);
     } else {
-        int sx = CX[a] ? wrap1(x - CX[a], g.nx) : x;
-        int sy = CY[a] ? wrap1(y - CY[a], g.ny) : y;
-        s = (sz * g.ny + sy) * g.nx + sx;
-        ha = a;
+        n.zm = wrap1(z - 1, g.nz);
+        n.zp = wrap1(z + 1, g.nz);
+        n.bbm = n.bbp = false;
     }
+    return n;
+}
+
+template <typename R, typename HS>
+__device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
+                                   const PullNbr &n, int x, int y, int z, int r, int a)
+{
+    // source s = r - c_a
+    const int sx = CX[a] > 0 ? n.xm : (CX[a] < 0 ? n.xp : x);
+    const int sy = CY[a] > 0 ? n.ym : (CY[a] < 0 ? n.yp : y);
+    const int sz = CZ[a] > 0 ? n.zm : (CZ[a] < 0 ? n.zp : z);
+    const bool bb = CZ[a] > 0 ? n.bbm : (CZ[a] < 0 ? n.bbp : false);
+    const int s = bb ? r : (sz * g.ny + sy) * g.nx + sx;
+    const int ha = bb ? OPP[a] : a;
     const V4<R> q = ru[s];
     const D ux = q.y, uy = q.z, uz = q.w;
     D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
@@ -229,10 +250,11 @@ __device__ __forceinline__ void pull_moments(const Geom &g, const V4<R> *__restr
                                              int x, int y, int z, D &rho, D &jx, D &jy, D &jz)
 {
     const int r = (z * g.ny + y) * g.nx + x;
+    const PullNbr n = pull_nbr(g, x, y, z);
     rho = jx = jy = jz = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        const D f = fpull<R, HS>(g, ru, h, x, y, z, r, a);
+        const D f = fpull<R, HS>(g, ru, h, n, x, y, z, r, a);
         rho += f;
         if (CX[a]) jx += D(CX[a]) * f;
         if (CY[a]) jy += D(CY[a]) * f;
@@ -1328,9 +1350,10 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ F
     // the order of pull_moments)
     D f[Q];
     D rho = 0, jx = 0, jy = 0, jz = 0;
+    const PullNbr nbr = pull_nbr(g, x, y, z);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        f[a] = fpull<R, HS>(g, ru_in, h_in, x, y, z, r, a);
+        f[a] = fpull<R, HS>(g, ru_in, h_in, nbr, x, y, z, r, a);
         rho += f[a];
         if (CX[a]) jx += D(CX[a]) * f[a];
         if (CY[a]) jy += D(CY[a]) * f[a];
@@ -1412,9 +1435,10 @@ __global__ __launch_bounds__(256) void k_populations(Geom g, const V4<R> *__rest
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const int r = (z * g.ny + y) * g.nx + x;
+    const PullNbr n = pull_nbr(g, x, y, z);
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-        if (a >= a0 && a < a0 + 8) f[(long long)(a - a0) * g.N + i] = R(fpull<R, HS>(g, ru, h, x, y, z, r, a));
+        if (a >= a0 && a < a0 + 8) f[(long long)(a - a0) * g.N + i] = R(fpull<R, HS>(g, ru, h, n, x, y, z, r, a));
 }
 
 // FP64 plane sums of rho, u_x and rho*u_x; one block per z-plane, fixed
