@@ -931,34 +931,51 @@ __device__ __forceinline__ void sh_quad(const R (&gm)[4], const V4<R> (&sm)[4], 
 // u1 = j/rho + (g + F^mf)/2 into the padded (rho, u1) array with its images,
 // and F^mf
 template <typename R>
-__device__ __forceinline__ void mf_finish(const Geom &g, const Pad &p, int x, int y, int z, R rr, R Fx, R Fy, R Fz,
-                                          const R *__restrict__ jx, const R *__restrict__ jy,
-                                          const R *__restrict__ jz, R gx, R gy, R gz, V4<R> *__restrict__ ru1_p,
-                                          V4<R> *__restrict__ fmf)
+__device__ __forceinline__ void mf_finish_v(const Geom &g, const Pad &p, int x, int y, int z, R rr, R Fx, R Fy,
+                                            R Fz, R jxi, R jyi, R jzi, R gx, R gy, R gz, V4<R> *__restrict__ ru1_p,
+                                            V4<R> *__restrict__ fmf)
 {
     const int i = (z * g.ny + y) * g.nx + x;
     V4<R> v = {R(0), R(0), R(0), R(0)};
     if (zfluid(g, z)) {
         plane_force(g, z, gx, gy, gz);
         const R inv = R(1) / rr;
-        v = V4<R>{rr, jx[i] * inv + R(0.5) * (gx + Fx), jy[i] * inv + R(0.5) * (gy + Fy),
-                  jz[i] * inv + R(0.5) * (gz + Fz)};
+        v = V4<R>{rr, jxi * inv + R(0.5) * (gx + Fx), jyi * inv + R(0.5) * (gy + Fy), jzi * inv + R(0.5) * (gz + Fz)};
     }
     for_images(g, p, x, y, z, [&](int k) { ru1_p[k] = v; });
     fmf[i] = V4<R>{Fx, Fy, Fz, R(0)};
+}
+template <typename R>
+__device__ __forceinline__ void mf_finish(const Geom &g, const Pad &p, int x, int y, int z, R rr, R Fx, R Fy, R Fz,
+                                          const R *__restrict__ jx, const R *__restrict__ jy,
+                                          const R *__restrict__ jz, R gx, R gy, R gz, V4<R> *__restrict__ ru1_p,
+                                          V4<R> *__restrict__ fmf)
+{
+    const int i = (z * g.ny + y) * g.nx + x;
+    mf_finish_v<R>(g, p, x, y, z, rr, Fx, Fy, Fz, jx[i], jy[i], jz[i], gx, gy, gz, ru1_p, fmf);
 }
 
 // F = rho (g + F^mf + c_v sum k (k.W)) and the traceless SMDB field
 // A = cA rho (sum_e (k_j W_i + k_i W_j)) minus its trace / 3
 template <typename R>
+__device__ __forceinline__ void sh_finish_v(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
+                                            R gx, R gy, R gz, int smdb, const V4<R> &fm, R *__restrict__ Fo,
+                                            R *__restrict__ Ao);
+template <typename R>
 __device__ __forceinline__ void sh_finish(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
                                           R gx, R gy, R gz, int smdb, const V4<R> *__restrict__ fmf,
                                           R *__restrict__ Fo, R *__restrict__ Ao)
 {
+    sh_finish_v<R>(g, x, y, z, r0, acc, cv, cA, gx, gy, gz, smdb, fmf[(z * g.ny + y) * g.nx + x], Fo, Ao);
+}
+template <typename R>
+__device__ __forceinline__ void sh_finish_v(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
+                                            R gx, R gy, R gz, int smdb, const V4<R> &fm, R *__restrict__ Fo,
+                                            R *__restrict__ Ao)
+{
     const long long N = g.N;
     const int i = (z * g.ny + y) * g.nx + x;
     plane_force(g, z, gx, gy, gz);
-    const V4<R> fm = fmf[i];
     Fo[i] = r0 * (gx + fm.x + cv * acc[0]);
     Fo[N + i] = r0 * (gy + fm.y + cv * acc[1]);
     Fo[2 * N + i] = r0 * (gz + fm.z + cv * acc[2]);
@@ -1161,10 +1178,20 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     ShellRings<R, R, TX, TY, TZ, NR, NG, 2> rg;
     rg.init(lds_raw, p, RC, tc, rho_p, gam_p);
+    // the node's own inputs of mf_finish, fetched now and pinned after the
+    // first c-step so that their latency hides behind it
+    const int xc = min(x, g.nx - 1), yc = min(y, g.ny - 1), zc = min(z, g.nz - 1), ic = (zc * g.ny + yc) * g.nx + xc;
+    R rr = rho_p[pidx(p, xc, yc, zc)], jxi = jx[ic], jyi = jy[ic], jzi = jz[ic];
     R fx = 0, fy = 0, fz = 0;
     static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
         constexpr int c = decltype(ci)::value;
         constexpr int S = (c + RC) & 1;
+        if constexpr (c == -RC + 1) {
+            pin(rr);
+            pin(jxi);
+            pin(jyi);
+            pin(jzi);
+        }
         rg.template begin<S>(c, p, rho_p, gam_p);
         const R *pc = rg.plane(c) - (RC + RC * LX);
         const R *gc = rg.gamma(c) - (O + O * LXg);
@@ -1199,8 +1226,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
         rg.template end<S>(c);
     });
     if (!valid) return;
-    mf_finish<R>(g, p, x, y, z, rho_p[pidx(p, x, y, z)], cmf * fx, cmf * fy, cmf * fz, jx, jy, jz, gx, gy, gz,
-                 ru1_p, fmf);
+    mf_finish_v<R>(g, p, x, y, z, rr, cmf * fx, cmf * fy, cmf * fz, jxi, jyi, jzi, gx, gy, gz, ru1_p, fmf);
 }
 
 template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
@@ -1220,10 +1246,17 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
     ShellRings<R, V4<R>, TX, TY, TZ, NR, NG> rg;
     rg.init(lds_raw, p, RC, tc, ru1_p, gam_p);
     const V4<R> c0 = ru1_p[pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1))];
+    // F^mf of the node for sh_finish, fetched now, pinned after the first c-step
+    V4<R> fm = fmf[(min(z, g.nz - 1) * g.ny + min(y, g.ny - 1)) * g.nx + min(x, g.nx - 1)];
     R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
         constexpr int c = decltype(ci)::value;
         constexpr int S = (c + RC) & 1;
+        if constexpr (c == -RC + 1) {
+            pin(fm.x);
+            pin(fm.y);
+            pin(fm.z);
+        }
         rg.template begin<S>(c, p, ru1_p, gam_p);
         const V4<R> *pc = rg.plane(c) - (RC + RC * LX);
         const R *gc = rg.gamma(c) - (O + O * LXg);
@@ -1302,7 +1335,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
         rg.template end<S>(c);
     });
     if (!valid) return;
-    sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
+    sh_finish_v<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fm, Fo, Ao);
 }
 
 // F (3N) and A (xx, yy, zz, xy, xz, yz; 6N) for nonlocal = 0: F = rho g
