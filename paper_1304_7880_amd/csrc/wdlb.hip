@@ -397,11 +397,15 @@ inline dim3 grid1(long long N, int bs) { return dim3((unsigned)((N + bs - 1) / b
 enum { K_MOMENTS = 0, K_DENSITY, K_MEANFIELD, K_SHELL, K_COLLIDE };
 const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide"};
 
+// Timing events are created without the system-scope fence: a default event
+// writes back and invalidates the caches when it is recorded, which slows
+// the timed kernel's successor and inflates the measured times.  prof_flush
+// synchronises the stream before it reads them, so no fence is needed.
 hipEvent_t take_event(wdlb_ctx *c)
 {
     if (c->ev_free.empty()) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     hipEvent_t e = c->ev_free.back();
