@@ -338,3 +338,32 @@ def test_graph_replay_equals_eager_steps(prec):
     assert ctxs[0].get_step() == ctxs[1].get_step() == 20
     for ctx in ctxs:
         ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp32"])
+def test_kernel_timing_changes_no_result(prec):
+    """Timing every kernel with HIP events (wdlb_profile) runs the step launch
+    by launch with events between the kernels: the fields must be exactly those
+    of an untimed context, and every kernel must report a positive mean time."""
+    nx, ny, nz, sigma, eta, tau, g = 64, 16, 18, 6.0, 0.3, 0.9, (1e-4, 0.0, 0.0)
+    _say(f"timed vs untimed {nx}x{ny}x{nz} sigma={sigma} {prec}")
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=33)
+    ctxs = []
+    for timed in (True, False):
+        ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, g)
+        ctx.init_fields(n, u)
+        if timed:
+            ctx.profile(True)
+        ctxs.append(ctx)
+    for ctx in ctxs:
+        ctx.step(7)
+    times = ctxs[0].profile_read()
+    ctxs[0].profile(False)
+    outs = [ctx.read_fields(with_forces=True) for ctx in ctxs]
+    for k, name in enumerate(("rho", "u", "F", "A0")):
+        assert np.array_equal(outs[0][k], outs[1][k]), name
+    assert set(times) == {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide"}
+    for name, (ms, count) in times.items():
+        assert count == 7 and ms > 0, (name, ms, count)
+    for ctx in ctxs:
+        ctx.destroy()
