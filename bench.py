@@ -58,17 +58,19 @@ def device_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-PROFILE = os.path.join(ROOT, "profiles", "step_kernels_slab64.md")
+PROFILES = {"slab64": os.path.join(ROOT, "profiles", "step_kernels_slab64.md"),
+            "slab512": os.path.join(ROOT, "profiles", "step_kernels_slab512x512x256.md")}
+PROFILE = PROFILES["slab64"]
 
 
-def measured_traffic():
+def measured_traffic(profile=PROFILE):
     """Calibrated HBM bytes per launch of each step kernel, from the rocprofv3
-    counter runs summarised in PROFILE, or None if the device code changed
-    since they were taken."""
-    if not os.path.exists(PROFILE):
+    counter runs summarised in the profile file, or None if the device code
+    changed since they were taken."""
+    if not os.path.exists(profile):
         return None
     kv, traffic = {}, {}
-    for line in open(PROFILE):
+    for line in open(profile):
         if ":" not in line:
             continue
         key, val = line.split(":", 1)
@@ -262,6 +264,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
                          "calibrating HBM byte counters under a profiler)")
+    ap.add_argument("--workload", choices=("slab64", "slab512"), default="slab64",
+                    help="slab64: the 64x64x64 slit (default); slab512: the 512x512x256 slab at sigma = 10 "
+                         "(no CPU baseline or serving leg)")
+    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
+                    help="population storage of the timed lattice")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
                     help="run the transport experiments instead (comma list of bulk, sound, slit; default all); "
                          "one JSON line")
@@ -273,9 +280,11 @@ def main():
 
     import torch
     from paper_1304_7880_amd import wdlb
-    from paper_1304_7880_amd.workloads import SLAB_64, initial_fields
+    from paper_1304_7880_amd.workloads import SLAB_64, SLAB_LARGE, initial_fields
 
-    w = SLAB_64
+    w = SLAB_64 if args.workload == "slab64" else SLAB_LARGE
+    if args.workload != "slab64":
+        args.no_cpu, args.serving = True, 0
     if not os.path.exists(wdlb.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
@@ -294,9 +303,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, "fp32", w.sigma, w.eta, w.tau, w.g, stream=stream)
-    n, u = initial_fields(w)
-    ctx.init_fields(n, u)
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, args.precision, w.sigma, w.eta, w.tau, w.g, stream=stream)
+    if w.noise or w.shear_amp:
+        n, u = initial_fields(w)
+        ctx.init_fields(n, u)
+    else:  # a uniform fluid at rest: no host fields to build and copy
+        ctx.init_uniform((0.0, 0.0, 0.0))
     ctx.step(args.warmup)
     ctx.sync()
 
@@ -330,7 +342,8 @@ def main():
     flops = shell_flops_per_node(w.sigma) * w.N
     achieved = flops / k_avg_s / 1e12
     J, upore, mass = ctx.read_flux()
-    traffic = measured_traffic()
+    # counter data were taken with FP32 storage on each workload's own profile
+    traffic = measured_traffic(PROFILES[args.workload]) if args.precision == "fp32" else None
     shell_traffic = traffic.get(shell_name) if traffic else None
     step_bytes = sum(traffic.values()) if traffic else None
 
@@ -346,9 +359,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
-        "data": "synthetic (seeded +-1% density noise, uniform start)",
+        "data": ("synthetic (seeded +-1% density noise, uniform start)" if w.noise
+                 else "synthetic (uniform fluid at rest)"),
         "config": {"workload": w.name, "nodes": w.N, "sigma": w.sigma, "eta": w.eta, "tau": w.tau,
-                   "precision": "fp32 populations (f - feq encoding), fp64 reductions"},
+                   "precision": ("fp32 populations (f - feq encoding), fp64 reductions" if args.precision == "fp32"
+                                 else "bf16 f - feq (fp32 closure populations), fp32 arithmetic, fp64 reductions")},
         "roofline": {"bound": "alu", "kernel": shell_name, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": shell_traffic,
