@@ -181,6 +181,27 @@ __device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int ti
     return t;
 }
 
+// The node of a thread in the per-node kernels (moments, collide): blocks of
+// 256 threads cover (1 << lgx) x (256 >> lgx) tiles in x, y of one plane,
+// and the blocks of one XCD (consecutive in xcd_tile order) take the planes
+// of one tile in turn, so the planes z -+ 1 that a pull reads were fetched
+// into that XCD's L2 by its previous blocks.
+struct NodeTiles {
+    int tx, ty, nzr, lgx;  // tiles in x and y, planes, log2 of the tile width
+};
+
+__device__ __forceinline__ bool node_tiled(const Geom &g, const NodeTiles &t, int &x, int &y, int &z, long long &i)
+{
+    const int lid = xcd_tile(blockIdx.x, t.tx * t.ty * t.nzr);
+    z = lid % t.nzr;
+    const int tt = lid / t.nzr;
+    x = ((tt % t.tx) << t.lgx) + ((int)threadIdx.x & ((1 << t.lgx) - 1));
+    y = (tt / t.tx) * (256 >> t.lgx) + ((int)threadIdx.x >> t.lgx);
+    if (x >= g.nx || y >= g.ny) return false;
+    i = ((long long)z * g.ny + y) * g.nx + x;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // pull: the population arriving at (x, y, z) with velocity c_a,
 //   f_a = w_a rho_s (1 + P_a(u*_s)) + h_a(s),
@@ -322,14 +343,14 @@ __global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ 
 // steps 2-4
 // ---------------------------------------------------------------------------
 template <typename R, typename HS>
-__global__ __launch_bounds__(256) void k_moments(Geom g, Pad p, const V4<R> *__restrict__ ru,
+__global__ __launch_bounds__(256) void k_moments(Geom g, NodeTiles nt, Pad p, const V4<R> *__restrict__ ru,
                                                  const HS *__restrict__ h, R *__restrict__ rho_p,
                                                  R *__restrict__ jx, R *__restrict__ jy, R *__restrict__ jz,
                                                  int *flag)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long i;
     int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
+    if (!node_tiled(g, nt, x, y, z, i)) return;
     if (!zfluid(g, z)) {  // a gap plane of a stacked lattice: rho = 0 for every stencil
         for_images(g, p, x, y, z, [&](int k) { rho_p[k] = R(0); });
         jx[i] = jy[i] = jz[i] = R(0);
@@ -1361,14 +1382,15 @@ __global__ __launch_bounds__(256) void k_plainforce(Geom g, Pad p, const R *__re
 // so the deviation carries no momentum and the flow lives in u* alone.
 // READ: only u = (j + F/2)/rho is written (the fields of the current state).
 template <typename R, typename HS, bool READ>
-__global__ __launch_bounds__(256) void k_collide(Geom g, const R *__restrict__ Fi, const R *__restrict__ Ai,
-                                                 R omega, R ksrc, const V4<R> *__restrict__ ru_in,
-                                                 const HS *__restrict__ h_in, V4<R> *__restrict__ ru_out,
-                                                 HS *__restrict__ h_out, R *__restrict__ u_rd, uint64_t step)
+__global__ __launch_bounds__(256) void k_collide(Geom g, NodeTiles nt, const R *__restrict__ Fi,
+                                                 const R *__restrict__ Ai, R omega, R ksrc,
+                                                 const V4<R> *__restrict__ ru_in, const HS *__restrict__ h_in,
+                                                 V4<R> *__restrict__ ru_out, HS *__restrict__ h_out,
+                                                 R *__restrict__ u_rd, uint64_t step)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long i;
     int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
+    if (!node_tiled(g, nt, x, y, z, i)) return;
     const long long N = g.N;
     if (!zfluid(g, z)) {  // gap plane of a stacked lattice: no state
         if (READ) u_rd[i] = u_rd[N + i] = u_rd[2 * N + i] = R(0);

@@ -614,6 +614,10 @@ wdlb_status run_pass(wdlb_ctx *c)
     const Pad pd = c->pad;
     const int bs = 256;
     dim3 grid = grid1((long long)g.nx * g.ny * c->nz_run, bs);  // planes 0 .. nz_run - 1
+    // per-node kernels with pulls: tiles of 64 x 4 (16 x 16 for narrow lattices), planes swept per XCD
+    const int lgx = g.nx >= 64 ? 6 : (g.nx >= 32 ? 5 : 4);
+    const NodeTiles nt{(g.nx + (1 << lgx) - 1) >> lgx, (g.ny + (256 >> lgx) - 1) / (256 >> lgx), c->nz_run, lgx};
+    const dim3 gridt((unsigned)nt.tx * nt.ty * nt.nzr);
     const int cur = c->cur, nxt = cur ^ 1;
     auto *ru_in = (const V4<R> *)c->ru[cur];
     auto *h_in = (const HS *)c->h[cur];
@@ -621,7 +625,7 @@ wdlb_status run_pass(wdlb_ctx *c)
     const double s = p.sigma;
     wdlb_status st;
     st = launch(c, K_MOMENTS, [&] {
-        hipLaunchKernelGGL((k_moments<R, HS>), grid, dim3(bs), 0, c->stream, g, pd, ru_in, h_in, (R *)c->rho_p,
+        hipLaunchKernelGGL((k_moments<R, HS>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
                            (R *)c->jx, (R *)c->jy, (R *)c->jz, c->flag);
     });
     if (st != WDLB_OK) return st;
@@ -638,7 +642,7 @@ wdlb_status run_pass(wdlb_ctx *c)
         if (st != WDLB_OK) return st;
     }
     st = launch(c, K_COLLIDE, [&] {
-        hipLaunchKernelGGL((k_collide<R, HS, READ>), grid, dim3(bs), 0, c->stream, g, (const R *)c->F,
+        hipLaunchKernelGGL((k_collide<R, HS, READ>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
                            (const R *)c->A, R(1.0 / p.tau), R(1.0 - 0.5 / p.tau), ru_in, h_in, (V4<R> *)c->ru[nxt],
                            (HS *)c->h[nxt], (R *)c->u_rd, (uint64_t)c->step);
     });
