@@ -98,9 +98,23 @@ def cpu_baseline(w, budget_s: float = 12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": ref.threads(), "kind": "oracle",
+    cores = ref.threads()
+    # one step on one thread beside it (the oracle's serial rate)
+    ref.set_threads(1)
+    t1 = time.perf_counter()
+    st.step(1)
+    dt1 = time.perf_counter() - t1
+    ref.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{steps} step(s) of the full {w.nx}x{w.ny}x{w.nz} workload from the same initial state, "
-                      f"{dt:.1f} s, OpenMP over z-planes"}
+                      f"{dt:.1f} s, OpenMP over z-planes",
+            "single_thread_value": w.N / dt1 / 1e6, "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def _percentile(v, q):
