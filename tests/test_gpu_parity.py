@@ -49,6 +49,8 @@ CASES = [
     ("walled 16x16x14 sigma=4 (narrow tiles)", (16, 16, 14), True, 4.0, 0.3, 1.0, (2e-5, 0, 0), 3),
     # the largest compiled shell (reach 11) against the oracle's fields
     ("walled 22x21x26 sigma=10", (22, 21, 26), True, 10.0, 0.3, 0.9, (1e-4, 0, 0), 2),
+    # 64x4 tiles of the per-node kernels, ragged in x (70 = 64 + 6) and y (5 = 4 + 1)
+    ("walled 70x5x12 sigma=3 (per-node tiles ragged)", (70, 5, 12), True, 3.0, 0.3, 0.9, (1e-4, 2e-5, 0), 3),
 ]
 
 
