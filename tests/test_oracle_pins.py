@@ -170,6 +170,65 @@ def test_poiseuille_plain_bgk(tau):
     pred = g / (2 * nu) * ((H / 2) ** 2 - z ** 2) + g * (4 * lam ** 2 - 3) / (4 * lam)
     assert np.abs(ux_z - pred).max() < 1e-9 * pred.max()
     assert np.abs(n_z - 1).max() < 1e-12
+    # pore averages (the pore-averaged flux of the abstract; mass of Sec. 2):
+    # at rho = 1 the mass flux and the mean velocity both equal the mean of
+    # the profile, sum over z of (H^2/4 - z^2) = H (2 H^2 + 1) / 12, and the
+    # mass is the node count
+    mean_pred = g * (2 * H * H + 1) / (24 * nu) + g * (4 * lam ** 2 - 3) / (4 * lam)
+    assert abs(J - mean_pred) < 1e-9 * mean_pred
+    assert abs(upore - mean_pred) < 1e-9 * mean_pred
+    assert abs(M - H) < 1e-12 * H
+    col = Column(H, 4.0, tau, g=(g, 0.0, 0.0), walls=True, nonlocal_=False)
+    col.init(1.0, np.zeros(3))
+    col.step(int(40 * H * H / (nu * math.pi ** 2)))
+    _, ux_c, J_c, up_c, M_c = col.reduce()
+    assert np.abs(ux_c - pred).max() < 1e-9 * pred.max()
+    assert abs(J_c - mean_pred) < 1e-9 * mean_pred
+    assert abs(up_c - mean_pred) < 1e-9 * mean_pred
+    assert abs(M_c - H) < 1e-12 * H
+
+
+# --------------------------------------------------------------------------
+# Pore averages of a state whose density and velocity vary together (the
+# pore-averaged flux of the abstract and introduction; mass of Sec. 2).
+# f = f_eq(n, u) with the fields
+#     n = 1 + a cos(2 pi z/H) + a' cos(2 pi x/nx),
+#     u_x = c + b cos(2 pi z/H) + b' cos(2 pi x/nx),
+# no force and no hard-sphere fields, read at once: then u = j/rho = u_x
+# exactly and, over whole periods,
+#     J_pore = <n u_x> = c + a b/2 + a' b'/2,   u_pore = <u_x> = c,
+#     mass = N,   n(z) = 1 + a cos,   u_x(z) = c + b cos.
+# A flux normalised by a plane instead of the pore, or a density-weighted
+# mean velocity, fails these.
+# --------------------------------------------------------------------------
+def test_pore_averages_closed_form():
+    nx, ny, H = 6, 3, 8
+    a, a2, b, b2, c = 0.3, 0.2, 2e-3, -1.5e-3, 5e-4
+    zz, yy, xx = np.meshgrid(np.arange(H), np.arange(ny), np.arange(nx), indexing="ij")
+    cz, cx = np.cos(2 * math.pi * zz / H), np.cos(2 * math.pi * xx / nx)
+    n = (1 + a * cz + a2 * cx).ravel()
+    u = np.zeros((3, n.size))
+    u[0] = (c + b * cz + b2 * cx).ravel()
+    u[1] = 1e-3 * np.sin(2 * math.pi * yy / ny).ravel()
+    cfg = ref.Config(nx, ny, H, True, 4.0, 0.9, (0.0, 0.0, 0.0), nonlocal_=False)
+    st = ref.State.from_fields(cfg, n, u.ravel())
+    n_z, ux_z, J, upore, M = st.reduce()
+    z = np.arange(H)
+    assert np.abs(n_z - (1 + a * np.cos(2 * math.pi * z / H))).max() < 1e-13
+    assert np.abs(ux_z - (c + b * np.cos(2 * math.pi * z / H))).max() < 1e-15
+    J_exact = c + a * b / 2 + a2 * b2 / 2
+    assert abs(J - J_exact) < 1e-12 * abs(J_exact)
+    assert abs(upore - c) < 1e-12 * c
+    assert abs(M - nx * ny * H) < 1e-12 * nx * ny * H
+    # the column oracle on the x-independent part (a' = b' = 0)
+    col = Column(H, 4.0, 0.9, walls=True, nonlocal_=False)
+    uc = np.zeros((3, H))
+    uc[0] = c + b * np.cos(2 * math.pi * z / H)
+    col.init(1 + a * np.cos(2 * math.pi * z / H), uc)
+    _, _, J_c, up_c, M_c = col.reduce()
+    assert abs(J_c - (c + a * b / 2)) < 1e-12 * (c + a * b / 2)
+    assert abs(up_c - c) < 1e-12 * c
+    assert abs(M_c - H) < 1e-12 * H
 
 
 # --------------------------------------------------------------------------
