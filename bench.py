@@ -1,11 +1,13 @@
 """Benchmark of the WDLB time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--serving N]
 
-Workload: the 64x64x64 slit pore (H = 64) with sigma = 6, eta = 0.35,
-tau = 0.8, g_x = 1e-6 and a seeded +-1 % density noise, FP32 populations
-(the configuration on which the throughput metric is quoted).  Inputs are
-synthetic and resident on the device before the timed region starts.
+Workload (the headline): the 512x512x256 slit pore (H = 256) with
+sigma = 10, eta = 0.40, tau = 0.7, g_x = 5e-7, uniform start, populations
+stored in FP32 with the local kernels (pull, moments, collision) in FP64
+arithmetic, the stencil sums in FP32 and the reductions in FP64 (the mode
+that meets the 1e-5 accuracy bar).  Inputs are synthetic and resident on
+the device before the timed region starts.
 
 A step is one full WDLB step: moments, weighted density and contact values,
 mean-field shell sum, viscous/SMDB shell sum, and the forced collision with
@@ -13,8 +15,10 @@ the stream.  value = fluid nodes x steps / device time of the timed steps
 (MLUPS).  The dominant kernel (the viscous/SMDB shell sum) is timed with HIP
 events on the library's stream during the same run and priced against the
 chip's FP32 vector peak; HBM bytes per launch come from the rocprofv3
-counter summary in profiles/ while it matches the device sources.  The FP64
-CPU oracle is timed on a bounded sample on the host.  Prints one JSON line.
+counter summary in profiles/ while it matches the device sources.  Beside
+the headline: the same slab in the other storage modes, the 64x64x64 slit,
+the serving trace through the batched server and the plain loop, and the
+FP64 CPU oracle timed on a bounded sample on the host.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -60,16 +64,15 @@ def device_source_hash() -> str:
 
 PROFILES = {"slab64": os.path.join(ROOT, "profiles", "step_kernels_slab64.md"),
             "slab512": os.path.join(ROOT, "profiles", "step_kernels_slab512x512x256.md")}
-PROFILE = PROFILES["slab64"]
 
 
-def measured_traffic(profile=PROFILE):
-    """Calibrated HBM bytes per launch of each step kernel, from the rocprofv3
-    counter runs summarised in the profile file, or None if the device code
-    changed since they were taken."""
+def profile_figures(profile):
+    """(calibrated HBM bytes per launch, rocprofv3 mean duration in ms) of each
+    step kernel, from the rocprofv3 runs summarised in the profile file; both
+    empty if the device code changed since they were taken."""
     if not os.path.exists(profile):
-        return None
-    kv, traffic = {}, {}
+        return {}, {}
+    kv, traffic, dur = {}, {}, {}
     for line in open(profile):
         if ":" not in line:
             continue
@@ -79,13 +82,19 @@ def measured_traffic(profile=PROFILE):
             kv[key] = val
         elif key.startswith("traffic_bytes_per_launch "):
             traffic[key.split()[1]] = float(val)
-    if kv.get("device_source_sha256_16") != device_source_hash() or not traffic:
-        return None
-    return traffic
+        elif key.startswith("rocprof_mean_ms "):
+            dur[key.split()[1]] = float(val)
+    if kv.get("device_source_sha256_16") != device_source_hash():
+        return {}, {}
+    return traffic, dur
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
-    """The FP64 oracle on the same workload, stepped until budget_s elapsed."""
+def cpu_baseline(w, budget_s: float = 12.0, single_nxy: int = 16):
+    """The FP64 oracle on a bounded sample of the workload, from its initial
+    state: whole steps of the x,y sub-lattice w (all host threads, OpenMP over
+    z-planes) until budget_s has elapsed, then one step of a single_nxy^2 x nz
+    column of it on one thread.  Same sigma and nz, so the work per node is
+    that of the full workload."""
     from oracle import ref
     from paper_1304_7880_amd.workloads import initial_fields
     n, u = initial_fields(w)
@@ -99,10 +108,14 @@ def cpu_baseline(w, budget_s: float = 12.0):
             break
     dt = time.perf_counter() - t0
     cores = ref.threads()
-    # one step on one thread beside it (the oracle's serial rate)
+    del st
+    ws = w.with_(nx=single_nxy, ny=single_nxy)
+    n1, u1 = initial_fields(ws)
+    cfg1 = ref.Config(ws.nx, ws.ny, ws.nz, ws.walls_z, ws.sigma, ws.tau, ws.g)
+    st1 = ref.State.from_fields(cfg1, n1, u1)
     ref.set_threads(1)
     t1 = time.perf_counter()
-    st.step(1)
+    st1.step(1)
     dt1 = time.perf_counter() - t1
     ref.set_threads(cores)
     model = ""
@@ -112,14 +125,23 @@ def cpu_baseline(w, budget_s: float = 12.0):
     except OSError:
         pass
     return {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} step(s) of the full {w.nx}x{w.ny}x{w.nz} workload from the same initial state, "
-                      f"{dt:.1f} s, OpenMP over z-planes",
-            "single_thread_value": w.N / dt1 / 1e6, "cpu_model": model, "host_cpus": os.cpu_count()}
+            "sample": f"{steps} step(s) of the {w.nx}x{w.ny}x{w.nz} sub-lattice (sigma={w.sigma:g}: the same work "
+                      f"per node as the full slab) from the same initial state, {dt:.1f} s, OpenMP over z-planes",
+            "single_thread_value": ws.N / dt1 / 1e6,
+            "single_thread_sample": f"1 step of a {ws.nx}x{ws.ny}x{ws.nz} column, {dt1:.1f} s",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def _percentile(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def _lat_stats(lat, span, n_ok):
+    """Throughput over the converged requests and their latency percentiles."""
+    return {"solves_per_s": round(n_ok / span, 3) if span > 0 else None, "makespan_s": round(span, 3),
+            "p50_latency_s": None if not lat else round(_percentile(lat, 50), 4),
+            "p99_latency_s": None if not lat else round(_percentile(lat, 99), 4)}
 
 
 def serving_bench(n_req, planes, max_steps, plain=True):
@@ -128,8 +150,10 @@ def serving_bench(n_req, planes, max_steps, plain=True):
     [1e-7, 1e-5], 16x16 in x,y, sigma = 4, tau = 1; steady when the pore flux
     changes by < 1e-8 over 100 steps) in real time through the batched server
     and through the plain loop (one single-slit context at a time, FIFO, the
-    same kernels and the same steady-state test)."""
-    import numpy as np
+    same kernels and the same steady-state test).  Solves/s and the latency
+    percentiles count the requests that reached steady state; requests that
+    went unstable or hit the step cap are counted, with their latencies,
+    separately."""
     from paper_1304_7880_amd import wdlb
     from paper_1304_7880_amd.workloads import serving_requests
 
@@ -149,28 +173,38 @@ def serving_bench(n_req, planes, max_steps, plain=True):
     st = srv.stats()
     srv.destroy()
     print(f"serving: batched server done ({n_req} requests)", file=sys.stderr, flush=True)
+
+    def split(statuses, lats):
+        groups = {"converged": wdlb.OK, "unstable": wdlb.E_UNSTABLE, "not_converged": wdlb.E_NOT_CONVERGED}
+        out = {}
+        for name, code in groups.items():
+            lat = [l for sc, l in zip(statuses, lats) if sc == code]
+            out[name] = len(lat)
+            if name != "converged":
+                out[f"{name}_p50_latency_s"] = None if not lat else round(_percentile(lat, 50), 4)
+        return out
+
+    stat_b = [res.status for res, _ in res_b]
     lat_b = [res.t_done - res.t_submit for res, _ in res_b]
+    ok_lat_b = [l for sc, l in zip(stat_b, lat_b) if sc == wdlb.OK]
     span_b = max(res.t_done for res, _ in res_b) - min(res.t_submit for res, _ in res_b)
-    ok_b = [res.status == wdlb.OK for res, _ in res_b]
-    out = {"requests": n_req, "server_planes": planes,
-           "batched": {"solves_per_s": round(n_req / span_b, 3), "makespan_s": round(span_b, 3),
-                       "p50_latency_s": round(_percentile(lat_b, 50), 4),
-                       "p99_latency_s": round(_percentile(lat_b, 99), 4),
-                       "converged": int(sum(ok_b)),
-                       "unstable": int(sum(res.status == wdlb.E_UNSTABLE for res, _ in res_b)),
-                       "not_converged": int(sum(res.status == wdlb.E_NOT_CONVERGED for res, _ in res_b)),
-                       "max_resident": st["max_resident"],
-                       "mlups": round(st["node_updates"] / max(st["busy_s"], 1e-9) / 1e6, 1)}}
+    batched = _lat_stats(ok_lat_b, span_b, len(ok_lat_b))
+    batched.update(split(stat_b, lat_b))
+    batched.update(max_resident=st["max_resident"],
+                   mlups=round(st["node_updates"] / max(st["busy_s"], 1e-9) / 1e6, 1))
+    out = {"requests": n_req, "server_planes": planes, "precision": "fp32 storage, fp64 local arithmetic",
+           "counted": "solves/s and latency percentiles over the requests that reached steady state",
+           "batched": batched}
     if not plain:
         return out
 
     t0 = time.perf_counter()
-    lat_p, same, t_last = [], True, 0.0
+    lat_p, stat_p, same, t_last = [], [], True, 0.0
     for r, (rb, uxb) in zip(reqs, res_b):
         now = time.perf_counter() - t0
         if now < r.arrival_s:
             time.sleep(r.arrival_s - now)
-        ctx = wdlb.Context(16, 16, r.H, True, "fp32", sigma, r.eta, r.tau, (r.gx, 0.0, 0.0))
+        ctx = wdlb.Context(16, 16, r.H, True, "fp32_local64", sigma, r.eta, r.tau, (r.gx, 0.0, 0.0))
         ctx.init_uniform((0.0, 0.0, 0.0))
         steps, Jprev, status, J = 0, None, wdlb.OK, 0.0
         while True:
@@ -190,14 +224,16 @@ def serving_bench(n_req, planes, max_steps, plain=True):
         ctx.destroy()
         t_last = time.perf_counter() - t0
         lat_p.append(t_last - r.arrival_s)
+        stat_p.append(status)
         if len(lat_p) % 32 == 0:
             print(f"serving: plain loop {len(lat_p)}/{n_req}", file=sys.stderr, flush=True)
         same = same and status == rb.status and steps == rb.steps and (status != wdlb.OK or J == rb.j_pore)
     span_p = t_last - reqs[0].arrival_s
-    out["plain"] = {"solves_per_s": round(n_req / span_p, 3), "makespan_s": round(span_p, 3),
-                    "p50_latency_s": round(_percentile(lat_p, 50), 4),
-                    "p99_latency_s": round(_percentile(lat_p, 99), 4)}
-    out["speedup_solves_per_s"] = round(out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"], 2)
+    ok_lat_p = [l for sc, l in zip(stat_p, lat_p) if sc == wdlb.OK]
+    out["plain"] = _lat_stats(ok_lat_p, span_p, len(ok_lat_p))
+    out["plain"].update(split(stat_p, lat_p))
+    if out["plain"]["solves_per_s"] and out["batched"]["solves_per_s"]:
+        out["speedup_solves_per_s"] = round(out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"], 2)
     out["results_identical_batched_vs_plain"] = bool(same)
     return out
 
@@ -263,26 +299,86 @@ def transport_bench(parts=("bulk", "sound", "slit")):
             "bulk": bulk, "sound": sound, "slit": slits}
 
 
+SURVEY_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
+
+
+def timed_run(w, precision, steps, warmup, stream, init_fields=None):
+    """Warm up, then time exactly `steps` steps of workload w between
+    synchronisations, with HIP events on the library's stream around every
+    launch of the viscous/SMDB shell kernel; then a short per-kernel breakdown
+    after the timed region."""
+    import torch
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import initial_fields
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, precision, w.sigma, w.eta, w.tau, w.g, stream=stream)
+    if w.noise or w.shear_amp:
+        n, u = initial_fields(w)
+        ctx.init_fields(n, u)
+    else:  # a uniform fluid at rest: no host fields to build and copy
+        ctx.init_uniform((0.0, 0.0, 0.0))
+    ctx.step(warmup)
+    ctx.sync()
+    shell_name = "k_shell_s" if ctx.get_tile()[1] else "k_shell"
+    ctx.profile(True, kernels=["k_shell"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    dev_ms = e0.elapsed_time(e1)
+    k_ms, k_n = ctx.profile_read()["k_shell"]
+    ctx.profile(False)
+    nb = min(steps, 20)
+    ctx.profile(True)
+    ctx.step(nb)
+    kstats = ctx.profile_read()
+    ctx.profile(False)
+    J, upore, mass = ctx.read_flux()
+    ctx.destroy()
+    del ctx
+    torch.cuda.empty_cache()
+    return {"dev_ms": dev_ms, "wall_s": wall, "ms_per_step": dev_ms / steps,
+            "mlups": w.N * steps / (dev_ms * 1e-3) / 1e6, "shell_name": shell_name,
+            "shell_avg_ms": k_ms / k_n, "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kstats.items()},
+            "pore_flux": J}
+
+
+PRECISION_LABEL = {
+    "fp32_local64": "fp32 storage; fp32 stencil sums (weighted density, contact values, shell sums); fp64 arithmetic "
+                    "in the local kernels (pull, moments, collision); fp64 reductions",
+    "fp32": "fp32 storage and arithmetic; fp64 reductions",
+    "bf16": "bf16 f - feq storage (fp32 closure populations); fp32 arithmetic; fp64 reductions",
+    "bf16_local64": "bf16 f - feq storage (fp32 closure populations); fp32 stencil sums; fp64 arithmetic in the "
+                    "local kernels; fp64 reductions",
+    "fp64": "fp64 storage and arithmetic",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serving", type=int, default=64, metavar="N",
+    ap.add_argument("--serving", type=int, default=512, metavar="N",
                     help="requests of the serving trace replayed through the batched server and the plain loop "
                          "(0: skip)")
     ap.add_argument("--serving-planes", type=int, default=4096, help="z-planes of the serving lattice")
     ap.add_argument("--serving-max-steps", type=int, default=60000)
     ap.add_argument("--serving-no-plain", action="store_true", help="batched server only")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time only the headline (no other storage modes, no 64^3 slit)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (a plain copy kernel of known traffic, for "
                          "calibrating HBM byte counters under a profiler)")
-    ap.add_argument("--workload", choices=("slab64", "slab512"), default="slab64",
-                    help="slab64: the 64x64x64 slit (default); slab512: the 512x512x256 slab at sigma = 10 "
-                         "(no CPU baseline or serving leg)")
-    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
-                    help="population storage of the timed lattice")
+    ap.add_argument("--workload", choices=("slab512", "slab64"), default="slab512",
+                    help="slab512: the 512x512x256 slab at sigma = 10 (default); slab64: the 64x64x64 slit")
+    ap.add_argument("--precision", choices=tuple(PRECISION_LABEL), default="fp32_local64",
+                    help="storage and local arithmetic of the timed lattice")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
                     help="run the transport experiments instead (comma list of bulk, sound, slit; default all); "
                          "one JSON line")
@@ -294,11 +390,9 @@ def main():
 
     import torch
     from paper_1304_7880_amd import wdlb
-    from paper_1304_7880_amd.workloads import SLAB_64, SLAB_LARGE, initial_fields
+    from paper_1304_7880_amd.workloads import SLAB_64, SLAB_LARGE, SLAB_LARGE_SUB
 
-    w = SLAB_64 if args.workload == "slab64" else SLAB_LARGE
-    if args.workload != "slab64":
-        args.no_cpu, args.serving = True, 0
+    w = SLAB_LARGE if args.workload == "slab512" else SLAB_64
     if not os.path.exists(wdlb.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
@@ -317,58 +411,26 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, args.precision, w.sigma, w.eta, w.tau, w.g, stream=stream)
-    if w.noise or w.shear_amp:
-        n, u = initial_fields(w)
-        ctx.init_fields(n, u)
-    else:  # a uniform fluid at rest: no host fields to build and copy
-        ctx.init_uniform((0.0, 0.0, 0.0))
-    ctx.step(args.warmup)
-    ctx.sync()
 
-    # timed region: K steps bracketed by synchronisations; HIP events on the
-    # library's stream around every launch of the dominant kernel
-    shell_name = "k_shell_s" if ctx.get_tile()[1] else "k_shell"
-    ctx.profile(True, kernels=["k_shell"])
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    ctx.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.sync()
-    dev_ms = e0.elapsed_time(e1)
-    k_ms, k_n = ctx.profile_read()["k_shell"]
-    ctx.profile(False)
-
-    # per-kernel breakdown (events around every launch), after the timed region
-    nb = min(args.steps, 200)
-    ctx.profile(True)
-    ctx.step(nb)
-    kstats = ctx.profile_read()
-    ctx.profile(False)
-
-    ms_per_step = dev_ms / args.steps
-    mlups = w.N * args.steps / (dev_ms * 1e-3) / 1e6
-    k_avg_s = k_ms * 1e-3 / k_n
-    flops = shell_flops_per_node(w.sigma) * w.N
-    achieved = flops / k_avg_s / 1e12
-    J, upore, mass = ctx.read_flux()
-    # counter data were taken with FP32 storage on each workload's own profile
-    traffic = measured_traffic(PROFILES[args.workload]) if args.precision == "fp32" else None
-    shell_traffic = traffic.get(shell_name) if traffic else None
+    print(f"bench: {w.name}, {args.precision}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
+    r = timed_run(w, args.precision, args.steps, args.warmup, stream)
+    k_avg_s = r["shell_avg_ms"] * 1e-3
+    nS = shell_size(w.sigma)
+    flops36 = shell_flops_per_node(w.sigma) * w.N
+    ops26 = SURVEY_OPS_PER_OFFSET * nS * w.N
+    traffic, rp_ms = profile_figures(PROFILES[args.workload])
+    if args.precision != "fp32_local64":   # counters are taken in the default mode
+        traffic, rp_ms = {}, {}
+    shell = r["shell_name"]
     step_bytes = sum(traffic.values()) if traffic else None
-
     out = {
         "metric": "MLUPS (incl. nonlocal force)",
-        "value": round(mlups, 2),
+        "value": round(r["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(r["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -376,27 +438,46 @@ def main():
         "data": ("synthetic (seeded +-1% density noise, uniform start)" if w.noise
                  else "synthetic (uniform fluid at rest)"),
         "config": {"workload": w.name, "nodes": w.N, "sigma": w.sigma, "eta": w.eta, "tau": w.tau,
-                   "precision": ("fp32 populations (f - feq encoding), fp64 reductions" if args.precision == "fp32"
-                                 else "bf16 f - feq (fp32 closure populations), fp32 arithmetic, fp64 reductions")},
-        "roofline": {"bound": "alu", "kernel": shell_name, "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": shell_traffic,
-                     "avg_kernel_ms": round(k_avg_s * 1e3, 5),
-                     "flops_per_launch": flops},
+                   "precision": PRECISION_LABEL[args.precision]},
+        "roofline": {"bound": "alu", "kernel": shell,
+                     "achieved": round(ops26 / k_avg_s / 1e12, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(ops26 / k_avg_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": traffic.get(shell),
+                     "count": f"{SURVEY_OPS_PER_OFFSET:g} operations per shell offset x {nS} offsets x {w.N} nodes",
+                     "ops_per_launch": ops26,
+                     "achieved_36flop": round(flops36 / k_avg_s / 1e12, 3),
+                     "frac_36flop": round(flops36 / k_avg_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "avg_kernel_ms": round(r["shell_avg_ms"], 5),
+                     "avg_kernel_ms_rocprofv3": rp_ms.get(shell)},
         "step_hbm": None if step_bytes is None else {
-            "bytes_per_step": step_bytes, "achieved_GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
-            "peak_GBs": PEAK_HBM_GBS,
-            "frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
-        "kernels_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in kstats.items()},
-        "wall_s": round(wall, 4),
-        "pore_flux": J,
+            "bytes_per_step": step_bytes,
+            "achieved_GBs": round(step_bytes / (r["ms_per_step"] * 1e-3) / 1e9, 1), "peak_GBs": PEAK_HBM_GBS,
+            "frac": round(step_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "kernels_ms_per_step": {k: round(v, 5) for k, v in r["kernels_ms_per_step"].items()},
+        "wall_s": round(r["wall_s"], 4),
+        "pore_flux": r["pore_flux"],
     }
-    ctx.destroy()
+    if not args.no_extra:
+        modes = {}
+        for prec in ("fp32", "bf16") if args.workload == "slab512" else ():
+            print(f"bench: {w.name}, {prec}", file=sys.stderr, flush=True)
+            m = timed_run(w, prec, args.steps, args.warmup, stream)
+            modes[prec] = {"mlups": round(m["mlups"], 2), "ms_per_step": round(m["ms_per_step"], 5),
+                           "precision": PRECISION_LABEL[prec]}
+        if modes:
+            out["other_precisions"] = modes
+        if args.workload == "slab512":
+            print(f"bench: {SLAB_64.name}", file=sys.stderr, flush=True)
+            m = timed_run(SLAB_64, args.precision, 200, 20, stream)
+            out["slab64"] = {"workload": SLAB_64.name, "mlups": round(m["mlups"], 2),
+                             "ms_per_step": round(m["ms_per_step"], 5), "steps": 200,
+                             "kernels_ms_per_step": {k: round(v, 5) for k, v in m["kernels_ms_per_step"].items()}}
     if args.serving:
         out["serving"] = serving_bench(args.serving, args.serving_planes, args.serving_max_steps,
                                        plain=not args.serving_no_plain)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w)
+        print("bench: cpu oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(SLAB_LARGE_SUB if args.workload == "slab512" else w)
     print(json.dumps(out), flush=True)
 
 

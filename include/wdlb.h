@@ -44,7 +44,7 @@ extern "C" {
 
 typedef enum {
     WDLB_OK = 0,
-    WDLB_E_INVAL = 1,          /* bad argument: shape, sigma < 1, tau <= 1/2, eta outside (0,1), size */
+    WDLB_E_INVAL = 1,          /* bad argument: shape, sigma outside [1, 16], tau <= 1/2, eta outside (0,1), size */
     WDLB_E_NOMEM = 2,          /* workspace smaller than wdlb_workspace_size reports */
     WDLB_E_HIP = 3,            /* a HIP call failed; wdlb_last_error has its message */
     WDLB_E_UNSTABLE = 4,       /* non-finite or non-positive density, or a midpoint packing fraction >= 1 */
@@ -52,10 +52,17 @@ typedef enum {
     WDLB_E_NOT_CONVERGED = 6   /* a serving request hit its step cap */
 } wdlb_status;
 
+/* Precision modes.  Storage is that of the populations and the per-step
+ * fields; the stencil sums (weighted density, contact values, shell sums)
+ * run in the storage's arithmetic (FP32 for the BF16 mode); the local
+ * kernels (pull, moments, collision) in the arithmetic named; reductions
+ * (plane means, pore averages, the serving convergence test) in FP64. */
 typedef enum {
     WDLB_FP64 = 0,             /* FP64 storage and arithmetic */
-    WDLB_FP32 = 1,             /* FP32 storage and arithmetic, FP64 reductions */
-    WDLB_BF16_NEQ = 2          /* BF16 storage of f - f_eq, FP32 arithmetic */
+    WDLB_FP32 = 1,             /* FP32 storage and arithmetic */
+    WDLB_BF16_NEQ = 2,         /* BF16 storage of f - f_eq (FP32 closure populations), FP32 arithmetic */
+    WDLB_FP32_LOCAL64 = 3,     /* FP32 storage, FP64 arithmetic in the local kernels */
+    WDLB_BF16_NEQ_LOCAL64 = 4  /* BF16 f - f_eq storage, FP64 arithmetic in the local kernels */
 } wdlb_precision;
 
 typedef struct wdlb_ctx wdlb_ctx;  /* opaque */
@@ -83,8 +90,9 @@ typedef struct {
     int32_t smdb;
 } wdlb_params;
 
-/* Bytes of device workspace a context with this lattice needs (independent
- * of sigma up to sigma = 24).  *bytes receives the size. */
+/* Bytes of device workspace a context with this lattice needs (the same for
+ * every sigma the library accepts, 1 <= sigma <= 16).  *bytes receives the
+ * size. */
 wdlb_status wdlb_workspace_size(const wdlb_lattice_desc *desc, const wdlb_params *params, size_t *bytes);
 
 /* Create a context on the current HIP device.  d_workspace: device memory of
@@ -113,23 +121,35 @@ wdlb_status wdlb_step(wdlb_ctx *ctx, int64_t nsteps);
  * met a non-finite or non-positive density or a packing fraction >= 1. */
 wdlb_status wdlb_sync(wdlb_ctx *ctx);
 
-/* Fields at the current time (Sec. 5, step 4): density h_n[N] and velocity
- * h_u[3N] = (j + F/2)/rho, FP64 host arrays.  Either pointer may be NULL.
+/* Fields at the current time (Sec. 5, step 4: the new density and velocity
+ * computed from the evolved populations): density h_n[N] = sum_a f_a and
+ * velocity h_u[3N] = (j + F/2)/rho, the velocity of the trapezoidal forcing
+ * of Sec. 5, step 3.  FP64 host arrays.  Either pointer may be NULL.
  * Synchronises. */
 wdlb_status wdlb_read_fields(wdlb_ctx *ctx, double *h_n, double *h_u);
 
-/* As wdlb_read_fields plus the total force density h_F[3N] =
- * rho (g + F^mf + F^v) and the traceless symmetric SMDB field h_A0[9N]
- * (row-major 3x3 per node).  Any pointer may be NULL. */
+/* As wdlb_read_fields plus the fields of Sec. 5, step 2 at the current time:
+ * the total force density h_F[3N] = n (g + F^mf + F^v), the external force of
+ * eq. (1) plus the hydrodynamic collision term C_i = n (F^mf + F^v) of the
+ * decomposition in Sec. 3 (mean-field force and the velocity-dependent part
+ * of eq. campoc), and the traceless symmetric SMDB field h_A0[9N] of
+ * eq. campod (row-major 3x3 per node).  Any pointer may be NULL. */
 wdlb_status wdlb_read_fields_ex(wdlb_ctx *ctx, double *h_n, double *h_u, double *h_F, double *h_A0);
 
-/* Plane means at the current time, reduced on the device in FP64:
- * h_n_z[nz] = <rho>_xy and h_ux_z[nz] = <u_x>_xy.  Either may be NULL. */
+/* Plane means at the current time of the fields of Sec. 5, step 4 (density
+ * and velocity recomputed from the evolved populations), reduced on the
+ * device in FP64: h_n_z[nz] = <rho>_xy and h_ux_z[nz] = <u_x>_xy, the
+ * density and flow profiles across the slit of the confinement experiments
+ * of Sec. 5.  Either may be NULL. */
 wdlb_status wdlb_read_profiles(wdlb_ctx *ctx, double *h_n_z, double *h_ux_z);
 
-/* Pore-averaged properties at the current time (FP64 device reductions):
- * j_pore = sum(rho u_x)/N (mass flux), u_pore = mean over z of <u_x>_xy,
- * mass = sum(rho).  Any pointer may be NULL. */
+/* Pore-averaged properties at the current time (the pore-averaged transport
+ * quantities of the abstract and introduction, from which the effective
+ * viscosity of the slit experiment of Sec. 5 follows), FP64 device
+ * reductions of the Sec. 5, step 4 fields: j_pore = sum(rho u_x)/N (mass
+ * flux per node), u_pore = mean over z of <u_x>_xy, mass = sum(rho) (the
+ * particle number conserved by the collision operator, Sec. 2).  Any pointer
+ * may be NULL. */
 wdlb_status wdlb_read_flux(wdlb_ctx *ctx, double *j_pore, double *u_pore, double *mass);
 
 /* Current post-stream populations f_a (19N, FP64, order above). */
@@ -260,9 +280,12 @@ wdlb_status wdlb_server_create(const wdlb_lattice_desc *desc, const wdlb_server_
 /* Queue a request; *id identifies it.  WDLB_E_INVAL if it can never fit or
  * its parameters are invalid. */
 wdlb_status wdlb_server_submit(wdlb_server *srv, const wdlb_request *req, uint64_t *id);
-/* The request's state; when finished and h_ux_z is not NULL, its plane means
- * <u_x>_xy (H values, FP64). */
-wdlb_status wdlb_server_poll(wdlb_server *srv, uint64_t id, wdlb_result *res, double *h_ux_z);
+/* The request's state into *res.  When the request has finished and h_ux_z
+ * is not NULL, also its plane means <u_x>_xy: res->H values (FP64) written
+ * to h_ux_z, a host buffer of n_ux doubles; WDLB_E_INVAL (and nothing
+ * written to h_ux_z) when n_ux < res->H.  *res is filled in either case, so
+ * a first call with h_ux_z = NULL tells the size. */
+wdlb_status wdlb_server_poll(wdlb_server *srv, uint64_t id, wdlb_result *res, double *h_ux_z, int32_t n_ux);
 /* Block until every submitted request has finished. */
 wdlb_status wdlb_server_drain(wdlb_server *srv);
 wdlb_status wdlb_server_stats_get(wdlb_server *srv, wdlb_server_stats *st);

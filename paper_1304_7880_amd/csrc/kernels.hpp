@@ -206,16 +206,17 @@ __device__ __forceinline__ bool node_tiled(const Geom &g, const NodeTiles &t, in
 // pull: the population arriving at (x, y, z) with velocity c_a,
 //   f_a = w_a rho_s (1 + P_a(u*_s)) + h_a(s),
 // from the source s = r - c_a, or by half-way bounce-back from r itself.
-// The pull, the moments and the collision run in FP64 arithmetic: near a
-// wall u* has a large wall-normal part (half the mean-field force per unit
-// mass) next to a tiny flow part, and FP32 products c.u* and sums of
-// populations of size w rho lose the flow to rounding.  FP64 sums of the
-// stored parts are exact enough that no special summation order is needed.
-// On gfx950 an FP64 FMA issues at half the FP32 rate, and this part is a
-// few percent of the step's arithmetic; storage keeps the precision of the
-// mode.
+// The local kernels (moments, collision) work with
+//   phi_a = f_a - w_a rho_r = w_a (rho_s - rho_r) + [w_a rho_s P_a(u*_s) + h_a(s)],
+// rho_r the node's own stored density: every term is small, so sums of phi
+// keep their absolute accuracy in FP32 (the large w_a rho parts cancel
+// exactly in the difference rho_s - rho_r instead of in a sum of 19
+// populations of size w rho, which would lose the flow to rounding).  Then
+//   rho = rho_r + sum_a phi_a,  j = sum_a c_a phi_a,
+//   f_a - feq_a(rho, u) = phi_a - w_a (delta + rho P_a(u)),  delta = rho - rho_r.
+// D is the arithmetic type of these kernels: the storage type, or FP64 with
+// FP32 storage in the modes that keep FP64 local arithmetic.
 // ---------------------------------------------------------------------------
-typedef double D;
 
 // The neighbours a node pulls from, found once per node: the wrapped
 // coordinates x -+ 1, y -+ 1, z -+ 1 and whether the planes z - 1 and z + 1
@@ -247,9 +248,10 @@ __device__ __forceinline__ PullNbr pull_nbr(const Geom &g, int x, int y, int z)
     return n;
 }
 
-template <typename R, typename HS>
-__device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
-                                   const PullNbr &n, int x, int y, int z, int r, int a)
+// phi_a of the node r (see above); rho_r is the node's stored density
+template <typename R, typename HS, typename D>
+__device__ __forceinline__ D fpull_phi(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
+                                       const PullNbr &n, int x, int y, int z, int r, int a, R rho_r)
 {
     // source s = r - c_a
     const int sx = CX[a] > 0 ? n.xm : (CX[a] < 0 ? n.xp : x);
@@ -263,20 +265,23 @@ __device__ __forceinline__ D fpull(const Geom &g, const V4<R> *__restrict__ ru, 
     D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
     if (bb) cu = -cu;
     const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * (ux * ux + uy * uy + uz * uz);
-    return wgt<D>(a) * D(q.x) * (D(1) + P) + D(ldh<R, HS>(h, ha, g.N, s));
+    const D w = wgt<D>(a);
+    return w * (D(q.x) - D(rho_r)) + (w * D(q.x) * P + D(ldh<R, HS>(h, ha, g.N, s)));
 }
 
-template <typename R, typename HS>
+// delta = rho - rho_r and j of the node from its 19 pulled populations
+template <typename R, typename HS, typename D>
 __device__ __forceinline__ void pull_moments(const Geom &g, const V4<R> *__restrict__ ru, const HS *__restrict__ h,
-                                             int x, int y, int z, D &rho, D &jx, D &jy, D &jz)
+                                             int x, int y, int z, R &rho_r, D &delta, D &jx, D &jy, D &jz)
 {
     const int r = (z * g.ny + y) * g.nx + x;
     const PullNbr n = pull_nbr(g, x, y, z);
-    rho = jx = jy = jz = 0;
+    rho_r = ru[r].x;
+    delta = jx = jy = jz = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        const D f = fpull<R, HS>(g, ru, h, n, x, y, z, r, a);
-        rho += f;
+        const D f = fpull_phi<R, HS, D>(g, ru, h, n, x, y, z, r, a, rho_r);
+        delta += f;
         if (CX[a]) jx += D(CX[a]) * f;
         if (CY[a]) jy += D(CY[a]) * f;
         if (CZ[a]) jz += D(CZ[a]) * f;
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ 
     const long long i = i0 + t;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
+    using D = double;  // once per run: FP64 in every mode
     const V4<R> q = ru[i];
     const D qx = q.x, qy = q.y, qz = q.z, qw = q.w;
     const D uu = qy * qy + qz * qz + qw * qw;
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(256) void k_init(Geom g, const V4<R> *__restrict__ 
 // ---------------------------------------------------------------------------
 // steps 2-4
 // ---------------------------------------------------------------------------
-template <typename R, typename HS>
+template <typename R, typename HS, typename D>
 __global__ __launch_bounds__(256) void k_moments(Geom g, NodeTiles nt, Pad p, const V4<R> *__restrict__ ru,
                                                  const HS *__restrict__ h, R *__restrict__ rho_p,
                                                  R *__restrict__ jx, R *__restrict__ jy, R *__restrict__ jz,
@@ -356,8 +362,10 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, NodeTiles nt, Pad p, co
         jx[i] = jy[i] = jz[i] = R(0);
         return;
     }
-    D r, a, b, c;
-    pull_moments<R, HS>(g, ru, h, x, y, z, r, a, b, c);
+    R r0;
+    D dl, a, b, c;
+    pull_moments<R, HS, D>(g, ru, h, x, y, z, r0, dl, a, b, c);
+    const D r = D(r0) + dl;
     if (!(r > D(0)) || !(r < D(INFINITY))) raise_flag_at(g, flag, z, FLAG_RHO);
     const R rr = R(r);
     for_images(g, p, x, y, z, [&](int k) { rho_p[k] = rr; });
@@ -1381,7 +1389,7 @@ __global__ __launch_bounds__(256) void k_plainforce(Geom g, Pad p, const R *__re
 //   h*_a = (1 - omega)(f_a - feq_a(u)) + [feq_a(u) - feq_a(u*)] + ksrc (guo_a + sa_a)
 // so the deviation carries no momentum and the flow lives in u* alone.
 // READ: only u = (j + F/2)/rho is written (the fields of the current state).
-template <typename R, typename HS, bool READ>
+template <typename R, typename HS, typename D, bool READ>
 __global__ __launch_bounds__(256) void k_collide(Geom g, NodeTiles nt, const R *__restrict__ Fi,
                                                  const R *__restrict__ Ai, R omega, R ksrc,
                                                  const V4<R> *__restrict__ ru_in, const HS *__restrict__ h_in,
@@ -1401,19 +1409,21 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, NodeTiles nt, const R *
         ksrc = R(g.zp[z].ksrc);
     }
     const int r = (z * g.ny + y) * g.nx + x;
-    // the 19 pulled populations, kept for the collision (moments summed in
-    // the order of pull_moments)
+    // the 19 pulled populations as phi_a = f_a - w_a rho_r, kept for the
+    // collision (moments summed in the order of pull_moments)
     D f[Q];
-    D rho = 0, jx = 0, jy = 0, jz = 0;
+    D delta = 0, jx = 0, jy = 0, jz = 0;
     const PullNbr nbr = pull_nbr(g, x, y, z);
+    const R rho_r = ru_in[r].x;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        f[a] = fpull<R, HS>(g, ru_in, h_in, nbr, x, y, z, r, a);
-        rho += f[a];
+        f[a] = fpull_phi<R, HS, D>(g, ru_in, h_in, nbr, x, y, z, r, a, rho_r);
+        delta += f[a];
         if (CX[a]) jx += D(CX[a]) * f[a];
         if (CY[a]) jy += D(CY[a]) * f[a];
         if (CZ[a]) jz += D(CZ[a]) * f[a];
     }
+    const D rho = D(rho_r) + delta;
     const D inv = D(1) / rho;
     const D Fx = Fi[i], Fy = Fi[N + i], Fz = Fi[2 * N + i];
     const D ux = (jx + D(0.5) * Fx) * inv, uy = (jy + D(0.5) * Fy) * inv, uz = (jz + D(0.5) * Fz) * inv;
@@ -1437,7 +1447,7 @@ __global__ __launch_bounds__(256) void k_collide(Geom g, NodeTiles nt, const R *
         const D w = wgt<D>(a);
         const D cu = D(CX[a]) * ux + D(CY[a]) * uy + D(CZ[a]) * uz;
         const D P = D(3) * cu + D(4.5) * cu * cu - D(1.5) * uu;
-        const D fneq = f[a] - w * rho * (D(1) + P);
+        const D fneq = f[a] - w * (delta + rho * P);
         const D cF = D(CX[a]) * Fx + D(CY[a]) * Fy + D(CZ[a]) * Fz;
         const D guo = w * (D(3) * (cF - uF) + D(9) * cu * cF);
         const D cAc = D(CX[a] * CX[a]) * Axx + D(CY[a] * CY[a]) * Ayy + D(CZ[a] * CZ[a]) * Azz +
@@ -1491,9 +1501,12 @@ __global__ __launch_bounds__(256) void k_populations(Geom g, const V4<R> *__rest
     if (!node_of(g, i, x, y, z)) return;
     const int r = (z * g.ny + y) * g.nx + x;
     const PullNbr n = pull_nbr(g, x, y, z);
+    const R rho_r = ru[r].x;
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-        if (a >= a0 && a < a0 + 8) f[(long long)(a - a0) * g.N + i] = R(fpull<R, HS>(g, ru, h, n, x, y, z, r, a));
+        if (a >= a0 && a < a0 + 8)
+            f[(long long)(a - a0) * g.N + i] =
+                R(wgt<double>(a) * double(rho_r) + fpull_phi<R, HS, double>(g, ru, h, n, x, y, z, r, a, rho_r));
 }
 
 // FP64 plane sums of rho, u_x and rho*u_x; one block per z-plane, fixed

@@ -88,7 +88,7 @@ wdlb_params server_lattice_params(const wdlb_server_params *sp)
 bool server_params_ok(const wdlb_lattice_desc *d, const wdlb_server_params *sp)
 {
     if (!d || !sp) return false;
-    if (!d->walls_z || d->precision != WDLB_FP32) return false;
+    if (!d->walls_z || (d->precision != WDLB_FP32 && d->precision != WDLB_FP32_LOCAL64)) return false;
     if (!(sp->tol > 0) || sp->check_every < 1 || sp->max_steps < sp->check_every) return false;
     wdlb_params p = server_lattice_params(sp);
     return desc_ok(d) && params_ok(&p);
@@ -380,15 +380,18 @@ wdlb_status wdlb_server_submit(wdlb_server *S, const wdlb_request *r, uint64_t *
     return WDLB_OK;
 }
 
-wdlb_status wdlb_server_poll(wdlb_server *S, uint64_t id, wdlb_result *res, double *h_ux_z)
+wdlb_status wdlb_server_poll(wdlb_server *S, uint64_t id, wdlb_result *res, double *h_ux_z, int32_t n_ux)
 {
     if (!S || !res) return WDLB_E_INVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->entries.find(id);
     if (it == S->entries.end()) return WDLB_E_INVAL;
     *res = it->second.res;
-    if (h_ux_z && res->state == 2)
+    if (h_ux_z && res->state == 2) {
+        // the profile has the request's own H values: refuse a smaller buffer
+        if (n_ux < 0 || (size_t)n_ux < it->second.ux.size()) return WDLB_E_INVAL;
         std::copy(it->second.ux.begin(), it->second.ux.end(), h_ux_z);
+    }
     return WDLB_OK;
 }
 

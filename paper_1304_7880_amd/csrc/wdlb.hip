@@ -33,7 +33,8 @@ struct wdlb_ctx {
     hipStream_t stream;
     Geom g;
     Pad pad;
-    int prec;
+    int prec;          // wdlb_precision requested (storage and local arithmetic)
+    int store;         // its storage: WDLB_FP64, WDLB_FP32 or WDLB_BF16_NEQ
     size_t rsize;      // bytes of one real (compute type)
     size_t hsize;      // bytes of one stored h
     int hplanes;       // planes of h per node (19; 23 in the BF16 mode)
@@ -101,7 +102,13 @@ bool desc_ok(const wdlb_lattice_desc *d)
     long long N = (long long)d->nx * d->ny * d->nz;
     long long NP = (long long)(d->nx + 2 * MAX_REACH) * (d->ny + 2 * MAX_REACH) * (d->nz + 2 * MAX_REACH);
     if (N * 19 >= (1LL << 31) || NP >= (1LL << 31)) return false;
-    return d->precision == WDLB_FP32 || d->precision == WDLB_FP64 || d->precision == WDLB_BF16_NEQ;
+    return d->precision >= WDLB_FP64 && d->precision <= WDLB_BF16_NEQ_LOCAL64;
+}
+
+// the storage of a precision mode (the LOCAL64 modes store like their base)
+int storage_of(int prec)
+{
+    return prec == WDLB_FP32_LOCAL64 ? WDLB_FP32 : (prec == WDLB_BF16_NEQ_LOCAL64 ? WDLB_BF16_NEQ : prec);
 }
 
 bool params_ok(const wdlb_params *p)
@@ -159,8 +166,9 @@ Layout layout(const wdlb_lattice_desc *d)
     size_t N = (size_t)d->nx * d->ny * d->nz;
     Pad pm = make_pad(d, MAX_REACH);
     size_t NP = (size_t)pm.NP;
-    size_t r = d->precision == WDLB_FP64 ? 8 : 4;
-    size_t hs = d->precision == WDLB_FP64 ? 8 : (d->precision == WDLB_BF16_NEQ ? 2 : 4);
+    const int st = storage_of(d->precision);
+    size_t r = st == WDLB_FP64 ? 8 : 4;
+    size_t hs = st == WDLB_FP64 ? 8 : (st == WDLB_BF16_NEQ ? 2 : 4);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -169,7 +177,7 @@ Layout layout(const wdlb_lattice_desc *d)
     };
     for (int b = 0; b < 2; ++b) {
         L.off_ru[b] = take(4 * r * N);
-        L.off_h[b] = take((size_t)(d->precision == WDLB_BF16_NEQ ? hplanes<bf16>() : 19) * hs * N);
+        L.off_h[b] = take((size_t)(st == WDLB_BF16_NEQ ? hplanes<bf16>() : 19) * hs * N);
     }
     L.off_rho_p = take(r * NP);
     L.off_gam_p = take(8 * r * NP);
@@ -388,7 +396,7 @@ void drop_graphs(wdlb_ctx *c)
 wdlb_status tables(wdlb_ctx *c)
 {
     drop_graphs(c);  // launch parameters may change
-    if (c->prec == WDLB_FP64) return upload_tables<double>(c);
+    if (c->store == WDLB_FP64) return upload_tables<double>(c);
     return upload_tables<float>(c);
 }
 
@@ -607,7 +615,7 @@ wdlb_status launch_density(wdlb_ctx *c)
 
 // one pass of the step kernels on the current buffers; READ stops after the
 // fields (u = (j + F/2)/rho into u_rd) and leaves the state untouched
-template <typename R, typename HS, bool READ>
+template <typename R, typename HS, typename D, bool READ>
 wdlb_status run_pass(wdlb_ctx *c)
 {
     const Geom g = c->g;
@@ -625,7 +633,7 @@ wdlb_status run_pass(wdlb_ctx *c)
     const double s = p.sigma;
     wdlb_status st;
     st = launch(c, K_MOMENTS, [&] {
-        hipLaunchKernelGGL((k_moments<R, HS>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
+        hipLaunchKernelGGL((k_moments<R, HS, D>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
                            (R *)c->jx, (R *)c->jy, (R *)c->jz, c->flag);
     });
     if (st != WDLB_OK) return st;
@@ -642,7 +650,7 @@ wdlb_status run_pass(wdlb_ctx *c)
         if (st != WDLB_OK) return st;
     }
     st = launch(c, K_COLLIDE, [&] {
-        hipLaunchKernelGGL((k_collide<R, HS, READ>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
+        hipLaunchKernelGGL((k_collide<R, HS, D, READ>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
                            (const R *)c->A, R(1.0 / p.tau), R(1.0 - 0.5 / p.tau), ru_in, h_in, (V4<R> *)c->ru[nxt],
                            (HS *)c->h[nxt], (R *)c->u_rd, (uint64_t)c->step);
     });
@@ -658,9 +666,11 @@ template <bool READ>
 wdlb_status pass(wdlb_ctx *c)
 {
     switch (c->prec) {
-    case WDLB_FP64: return run_pass<double, double, READ>(c);
-    case WDLB_FP32: return run_pass<float, float, READ>(c);
-    default: return run_pass<float, bf16, READ>(c);
+    case WDLB_FP64: return run_pass<double, double, double, READ>(c);
+    case WDLB_FP32: return run_pass<float, float, float, READ>(c);
+    case WDLB_BF16_NEQ: return run_pass<float, bf16, float, READ>(c);
+    case WDLB_FP32_LOCAL64: return run_pass<float, float, double, READ>(c);
+    default: return run_pass<float, bf16, double, READ>(c);
     }
 }
 
@@ -687,7 +697,7 @@ wdlb_status copy_out(wdlb_ctx *c, const void *dev, size_t n, double *host)
 
 wdlb_status copy_out_r(wdlb_ctx *c, const void *dev, size_t n, double *host)
 {
-    return c->prec == WDLB_FP64 ? copy_out<double>(c, dev, n, host) : copy_out<float>(c, dev, n, host);
+    return c->store == WDLB_FP64 ? copy_out<double>(c, dev, n, host) : copy_out<float>(c, dev, n, host);
 }
 
 wdlb_status read_pass(wdlb_ctx *c)
@@ -742,9 +752,10 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->prm = *params;
     c->stream = (hipStream_t)desc->stream;
     c->prec = desc->precision;
-    c->rsize = c->prec == WDLB_FP64 ? 8 : 4;
-    c->hsize = c->prec == WDLB_FP64 ? 8 : (c->prec == WDLB_BF16_NEQ ? 2 : 4);
-    c->hplanes = c->prec == WDLB_BF16_NEQ ? hplanes<bf16>() : 19;
+    c->store = storage_of(c->prec);
+    c->rsize = c->store == WDLB_FP64 ? 8 : 4;
+    c->hsize = c->store == WDLB_FP64 ? 8 : (c->store == WDLB_BF16_NEQ ? 2 : 4);
+    c->hplanes = c->store == WDLB_BF16_NEQ ? hplanes<bf16>() : 19;
     c->g.nx = desc->nx;
     c->g.ny = desc->ny;
     c->g.nz = desc->nz;
@@ -850,7 +861,7 @@ static wdlb_status do_init(wdlb_ctx *c, int uniform, const double u0[3], const d
     double n0 = 6.0 * c->prm.eta / (M_PI * c->prm.sigma * c->prm.sigma * c->prm.sigma);
     c->cur = 0;
     if (!uniform) {
-        if (c->prec == WDLB_FP64) {
+        if (c->store == WDLB_FP64) {
             std::vector<V4<double>> v(N);
             for (size_t i = 0; i < N; ++i) v[i] = V4<double>{h_n[i], h_u[i], h_u[N + i], h_u[2 * N + i]};
             HIPCHK(c, hipMemcpyAsync(c->ru[0], v.data(), N * sizeof(V4<double>), hipMemcpyHostToDevice, c->stream));
@@ -865,7 +876,7 @@ static wdlb_status do_init(wdlb_ctx *c, int uniform, const double u0[3], const d
     }
     dim3 grid = grid1(g.N, 256);
     double ux = u0 ? u0[0] : 0, uy = u0 ? u0[1] : 0, uz = u0 ? u0[2] : 0;
-    switch (c->prec) {
+    switch (c->store) {
     case WDLB_FP64:
         if (uniform)
             hipLaunchKernelGGL((k_fill<double>), grid, dim3(256), 0, c->stream, g, (V4<double> *)c->ru[0], n0, ux,
@@ -914,7 +925,7 @@ wdlb_status wdlb_step(wdlb_ctx *c, int64_t nsteps)
     if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
     // pairs of steps by graph replay (not while kernels are timed, and not
     // in the BF16 mode, whose rounding dither is keyed by the step number)
-    if (c->graphs && c->prof == 0 && c->prec != WDLB_BF16_NEQ) {
+    if (c->graphs && c->prof == 0 && c->store != WDLB_BF16_NEQ) {
         while (nsteps >= 2) {
             hipGraphExec_t ex = nullptr;
             wdlb_status st = step_graph(c, &ex);
@@ -970,7 +981,7 @@ static wdlb_status planes(wdlb_ctx *c, std::vector<double> &out)
     wdlb_status st = read_pass(c);
     if (st != WDLB_OK) return st;
     const Geom g = c->g;
-    if (c->prec == WDLB_FP64)
+    if (c->store == WDLB_FP64)
         hipLaunchKernelGGL((k_planes<double>), dim3(g.nz), dim3(256), 0, c->stream, g, c->pad,
                            (const double *)c->rho_p, (const double *)c->u_rd, c->planes);
     else
@@ -1028,7 +1039,7 @@ wdlb_status wdlb_read_populations(wdlb_ctx *c, double *h_f)
     // 8 populations at a time through the gamma array (8 NP >= 8 N reals)
     for (int a0 = 0; a0 < 19; a0 += 8) {
         const int na = std::min(8, 19 - a0);
-        switch (c->prec) {
+        switch (c->store) {
         case WDLB_FP64:
             hipLaunchKernelGGL((k_populations<double, double>), grid, dim3(256), 0, c->stream, g,
                                (const V4<double> *)c->ru[cur], (const double *)c->h[cur], a0, (double *)c->scratch);
@@ -1068,7 +1079,7 @@ wdlb_status wdlb_save_state(wdlb_ctx *c, void *h_buf, size_t bytes)
     hd.ny = c->g.ny;
     hd.nz = c->g.nz;
     hd.walls = c->g.walls;
-    hd.precision = c->prec;
+    hd.precision = c->store;
     hd.pad = 0;
     hd.step = c->step;
     char *p = (char *)h_buf;
@@ -1088,7 +1099,7 @@ wdlb_status wdlb_load_state(wdlb_ctx *c, const void *h_buf, size_t bytes)
     StateHeader hd;
     memcpy(&hd, h_buf, sizeof(hd));
     if (memcmp(hd.magic, "WDLBST02", 8) != 0 || hd.nx != c->g.nx || hd.ny != c->g.ny || hd.nz != c->g.nz ||
-        hd.walls != c->g.walls || hd.precision != c->prec)
+        hd.walls != c->g.walls || hd.precision != c->store)
         return fail(c, WDLB_E_STATE, "state does not match this context");
     const char *p = (const char *)h_buf;
     const size_t N = (size_t)c->g.N;

@@ -39,7 +39,7 @@ def decay_fit(times, amps, k, skip_steps, floor=1e-6):
 
 
 def shear_wave_viscosity(eta, sigma=8.0, n=128, nxy=None, steps=5000, every=10, tau=1.0, amp=1e-4,
-                         smdb=True, precision="fp32", skip=0.2) -> ShearDecay:
+                         smdb=True, precision="fp32_local64", skip=0.2) -> ShearDecay:
     """Periodic box n x n x n (or nxy x nxy x n), u_x = amp sin(2 pi z / n)
     at rest density n0(eta); nu from decay_fit over the steps after the
     first `skip` fraction of the run."""
@@ -83,7 +83,7 @@ class SlitFlow:
 
 
 def slit_effective_viscosity(H, eta, sigma=8.0, g=1e-6, nxy=16, tau=1.0, tol=1e-8, every=100,
-                             max_steps=200000, smdb=True, precision="fp32") -> SlitFlow:
+                             max_steps=200000, smdb=True, precision="fp32_local64") -> SlitFlow:
     """Poiseuille flow between the walls of a slit of H fluid planes, run
     until the pore flux changes by less than tol (relative) over `every`
     steps; the effective viscosity is the one a parabolic profile of the
@@ -141,7 +141,7 @@ def carnahan_starling_c2(eta, kT=1.0 / 3.0):
 
 
 def longitudinal_wave(eta, sigma=8.0, n=128, nxy=None, steps=2000, every=2, tau=1.0, eps=1e-3, smdb=True,
-                      precision="fp32", skip=50, floor=1e-3) -> SoundWave:
+                      precision="fp32_local64", skip=50, floor=1e-3) -> SoundWave:
     """Periodic box n x n x n (or nxy x nxy x n) at rest with the density
     n0(eta) (1 + eps sin(2 pi z / n)): the standing sound wave's frequency and
     decay give c^2 and the longitudinal viscosity (fit_damped_cosine over the

@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(HERE, "libwdlb.so")
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_NOT_CONVERGED = range(7)
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSTABLE", 5: "E_STATE", 6: "E_NOT_CONVERGED"}
-FP64, FP32, BF16_NEQ = 0, 1, 2
+FP64, FP32, BF16_NEQ, FP32_LOCAL64, BF16_NEQ_LOCAL64 = 0, 1, 2, 3, 4
 NKERNELS = 5
 NTILES = 6
-PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ}
+PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ, "fp32_local64": FP32_LOCAL64,
+             "bf16_local64": BF16_NEQ_LOCAL64}
 
 # D3Q19 order of the library's populations (include/wdlb.h)
 CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
@@ -118,7 +119,7 @@ def load(path: str = LIB_PATH):
     L.wdlb_server_create.argtypes = [C.POINTER(LatticeDesc), C.POINTER(ServerParams), vp, C.c_size_t,
                                      C.POINTER(vp)]
     L.wdlb_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
-    L.wdlb_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result), dp]
+    L.wdlb_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result), dp, C.c_int32]
     L.wdlb_server_drain.argtypes = [vp]
     L.wdlb_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
     L.wdlb_server_last_error.argtypes = [vp]
@@ -184,9 +185,12 @@ class Context:
             raise WdlbError(st, f"{what}: {msg.decode() if msg else ''}")
 
     def destroy(self):
+        """Release the context and drop the reference to its workspace (the
+        library synchronises the stream first, so the memory is idle)."""
         if getattr(self, "h", None):
             self._L.wdlb_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -303,10 +307,11 @@ class Server:
     slits of any height up to nz - R stacked in one lattice of nz planes; the
     pool is a torch uint8 tensor; a worker thread in the library steps them."""
 
-    def __init__(self, nx, ny, nz, sigma=4.0, tol=1e-8, check_every=100, max_steps=100000, device="cuda"):
+    def __init__(self, nx, ny, nz, sigma=4.0, tol=1e-8, check_every=100, max_steps=100000, device="cuda",
+                 precision="fp32_local64"):
         import torch
         L = load()
-        self.desc = make_desc(nx, ny, nz, True, "fp32", None)
+        self.desc = make_desc(nx, ny, nz, True, precision, None)
         self.params = ServerParams(float(sigma), float(tol), int(check_every), 0, int(max_steps))
         n = C.c_size_t(0)
         st = L.wdlb_server_workspace_size(C.byref(self.desc), C.byref(self.params), C.byref(n))
@@ -331,13 +336,22 @@ class Server:
         return rid.value
 
     def poll(self, rid, H=None):
-        """(Result, u_x(z) plane means or None)."""
+        """(Result, u_x(z) plane means or None).  The profile buffer is sized
+        from the request's own H (a first call without a buffer); H, if
+        given, is only checked against it."""
         res = Result()
-        ux = np.zeros(H) if H else None
-        st = self._L.wdlb_server_poll(self.h, int(rid), C.byref(res), _ptr(ux) if ux is not None else None)
+        st = self._L.wdlb_server_poll(self.h, int(rid), C.byref(res), None, 0)
         if st != OK:
             raise WdlbError(st, "poll")
-        return res, (ux if res.state == 2 else None)
+        if res.state != 2:
+            return res, None
+        if H is not None and int(H) != res.H:
+            raise ValueError(f"request {rid} has H = {res.H}, not {H}")
+        ux = np.zeros(res.H)
+        st = self._L.wdlb_server_poll(self.h, int(rid), C.byref(res), _ptr(ux), ux.size)
+        if st != OK:
+            raise WdlbError(st, "poll")
+        return res, ux
 
     def drain(self):
         st = self._L.wdlb_server_drain(self.h)

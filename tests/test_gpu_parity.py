@@ -51,6 +51,12 @@ CASES = [
     ("walled 22x21x26 sigma=10", (22, 21, 26), True, 10.0, 0.3, 0.9, (1e-4, 0, 0), 2),
     # 64x4 tiles of the per-node kernels, ragged in x (70 = 64 + 6) and y (5 = 4 + 1)
     ("walled 70x5x12 sigma=3 (per-node tiles ragged)", (70, 5, 12), True, 3.0, 0.3, 0.9, (1e-4, 2e-5, 0), 3),
+    # shells with no compiled kernels: the table-driven shell and ball sums
+    ("walled 23x18x19 sigma=5 (table-driven shell)", (23, 18, 19), True, 5.0, 0.3, 0.9, (1e-4, 0, 0), 2),
+    ("periodic 14x13x15 sigma=5.5 (non-integer sigma)", (14, 13, 15), False, 5.5, 0.3, 0.9, (0, 2e-5, 1e-5), 2),
+    ("walled 33x10x20 sigma=7 (table-driven shell)", (33, 10, 20), True, 7.0, 0.25, 1.0, (1e-4, 0, 0), 2),
+    ("walled 27x26x30 sigma=12 (reach 12, beyond the compiled shells)", (27, 26, 30), True, 12.0, 0.2, 1.0,
+     (1e-4, 0, 0), 1),
 ]
 
 
@@ -154,10 +160,12 @@ def test_compiled_shell_equals_table_driven(sigma, prec):
         assert np.array_equal(out[0][k], out[1][k]), (name, _rel(out[0][k], out[1][k]))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_local64", 1e-5), ("fp32", 1e-4)])
 def test_small_slab_full_run(prec, tol):
     """The 4x4x16 slit (sigma = 4, eta = 0.2, tau = 1, g_x = 1e-6), 2000 steps:
-    n(z), u_x(z) and the pore-averaged flux against the oracle."""
+    n(z), u_x(z) and the pore-averaged flux against the oracle.  FP32 storage
+    with FP64 local arithmetic meets 1e-5; FP32 local arithmetic (measured
+    6e-5 on u_x(z), 1e-5 on the flux) is held to 1e-4."""
     w = SLAB_SMALL
     _say(f"slab {w.name} {prec}")
     n, u = initial_fields(w)

@@ -4,6 +4,8 @@ together.  Each result must be bit-identical alone and in a mix (no slit
 reads another's planes, and every node sums in a fixed order), must equal a
 plain single-slit context stepped as long, and must match the FP64 column
 oracle within the FP32 bar (1e-5 relative on u_x(z) and the pore flux).
+The server stores FP32 and runs the local kernels in FP64 (the mode that
+meets that bar).
 """
 import sys
 
@@ -60,7 +62,7 @@ def test_server_slot_equals_plain_context():
     from paper_1304_7880_amd import wdlb
     H, eta, gx, tau = REQS[3]
     (res, ux), = _serve([REQS[3], REQS[0]], 100, max_steps=700)[0][:1]
-    ctx = wdlb.Context(16, 16, H, True, "fp32", SIGMA, eta, tau, (gx, 0.0, 0.0))
+    ctx = wdlb.Context(16, 16, H, True, "fp32_local64", SIGMA, eta, tau, (gx, 0.0, 0.0))
     ctx.init_uniform((0.0, 0.0, 0.0))
     ctx.step(res.steps)
     _, ux_c = ctx.read_profiles()
