@@ -102,6 +102,24 @@ wdlb_status wdlb_workspace_size(const wdlb_lattice_desc *desc, const wdlb_params
 wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params, void *d_workspace,
                         size_t bytes, wdlb_ctx **out);
 
+/* Create a context without allocating device memory, for callers that
+ * cannot allocate (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc).  The same context as wdlb_create, whose
+ * workspace is instead a device array of WDLB_STATIC_WORKSPACE_BYTES that
+ * the library holds on every device it runs on until the process ends.  No
+ * device memory is allocated by this call or by stepping the context: it
+ * steps launch by launch (graph replay, whose capture allocates, starts off;
+ * wdlb_set_graphs can turn it on).  Limits and errors: WDLB_E_NOMEM when the
+ * lattice's wdlb_workspace_size exceeds the array (a 64^3 FP32 lattice needs
+ * about 120 MB); WDLB_E_STATE while another such context is alive on the
+ * current device (both would use the one array: calls that overlap on a
+ * device would race); WDLB_E_HIP if the array cannot be located.  The array
+ * keeps the contents of the last context that used it; creation clears what
+ * must start at zero and init writes the state.  wdlb_destroy (after the
+ * stream has drained) frees the array for the next context. */
+#define WDLB_STATIC_WORKSPACE_BYTES ((size_t)256 << 20)
+wdlb_status wdlb_create_static(const wdlb_lattice_desc *desc, const wdlb_params *params, wdlb_ctx **out);
+
 /* Replace sigma, tau, g, nonlocal, smdb (eta only matters for init). */
 wdlb_status wdlb_set_params(wdlb_ctx *ctx, const wdlb_params *params);
 

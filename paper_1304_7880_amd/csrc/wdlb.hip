@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -69,6 +70,7 @@ struct wdlb_ctx {
     int nz_run;        // planes the step kernels process (nz; fewer in a partly filled stacked lattice)
     int64_t step;
     bool inited;
+    int static_dev = -1;  // device whose static workspace this context holds (wdlb_create_static), else -1
     std::string err;
     // event timing of the step kernels
     int prof = 0;  // bit k: time kernel k
@@ -802,6 +804,63 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     return WDLB_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The static workspace of wdlb_create_static: one array per device in the
+// library's code object, so a context can be made without any device
+// allocation.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// used.  At most one context per device holds it at a time.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t STATIC_WS_BYTES = WDLB_STATIC_WORKSPACE_BYTES;
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES] = {};
+bool g_static_busy[STATIC_MAX_DEVICES] = {};
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+extern "C" {
+
+wdlb_status wdlb_create_static(const wdlb_lattice_desc *desc, const wdlb_params *params, wdlb_ctx **out)
+{
+    if (!out) return WDLB_E_INVAL;
+    *out = nullptr;
+    if (!desc_ok(desc) || !params_ok(params)) return WDLB_E_INVAL;
+    if (layout(desc).total > STATIC_WS_BYTES) return WDLB_E_NOMEM;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return WDLB_E_HIP;
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_busy[dev]) return WDLB_E_STATE;
+        if (!g_static_ptr[dev]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+                (void)hipGetLastError();
+                return WDLB_E_HIP;
+            }
+            g_static_ptr[dev] = p;
+        }
+        ws = g_static_ptr[dev];
+        g_static_busy[dev] = true;
+    }
+    // the same context as wdlb_create on a caller workspace; create clears
+    // the padded arrays and uploads the tables, init writes the state
+    wdlb_status st = wdlb_create(desc, params, ws, STATIC_WS_BYTES, out);
+    if (st != WDLB_OK) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[dev] = false;
+        return st;
+    }
+    (*out)->static_dev = dev;
+    (*out)->graphs = false;  // graph capture and instantiation allocate
+    return WDLB_OK;
+}
+
 wdlb_status wdlb_set_params(wdlb_ctx *c, const wdlb_params *params)
 {
     if (!c) return WDLB_E_INVAL;
@@ -1184,10 +1243,14 @@ void wdlb_destroy(wdlb_ctx *c)
 {
     if (!c) return;
     prof_flush(c);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    if (c->static_dev >= 0) {  // the stream has drained: the static workspace is free
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[c->static_dev] = false;
+    }
     delete c;
 }
 

@@ -28,7 +28,7 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
                [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
                [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
 
-SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
+SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_create_static", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
            "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     L.wdlb_workspace_size.argtypes = [C.POINTER(LatticeDesc), C.POINTER(Params), C.POINTER(C.c_size_t)]
     L.wdlb_create.argtypes = [C.POINTER(LatticeDesc), C.POINTER(Params), vp, C.c_size_t, C.POINTER(vp)]
+    L.wdlb_create_static.argtypes = [C.POINTER(LatticeDesc), C.POINTER(Params), C.POINTER(vp)]
     L.wdlb_set_params.argtypes = [vp, C.POINTER(Params)]
     L.wdlb_init_uniform.argtypes = [vp, dp]
     L.wdlb_init_fields.argtypes = [vp, dp, dp]
@@ -158,7 +159,10 @@ class Context:
     """One lattice on the current device; the workspace is a torch uint8 tensor."""
 
     def __init__(self, nx, ny, nz, walls_z=True, precision="fp32", sigma=4.0, eta=0.2, tau=1.0,
-                 g=(0.0, 0.0, 0.0), nonlocal_=True, smdb=True, stream=None, device="cuda"):
+                 g=(0.0, 0.0, 0.0), nonlocal_=True, smdb=True, stream=None, device="cuda", static=False):
+        """static=True: wdlb_create_static (the library's own device array as
+        the workspace; nothing is allocated), else wdlb_create on a torch
+        workspace."""
         import torch
         L = load()
         if stream is None:
@@ -168,13 +172,19 @@ class Context:
         self.params = make_params(sigma, eta, tau, g, nonlocal_, smdb)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.N = self.nx * self.ny * self.nz
-        nbytes = workspace_size(self.desc, self.params)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         h = C.c_void_p()
-        st = L.wdlb_create(C.byref(self.desc), C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
-                           nbytes, C.byref(h))
-        if st != OK:
-            raise WdlbError(st, "wdlb_create")
+        if static:
+            self.workspace = None
+            st = L.wdlb_create_static(C.byref(self.desc), C.byref(self.params), C.byref(h))
+            if st != OK:
+                raise WdlbError(st, "wdlb_create_static")
+        else:
+            nbytes = workspace_size(self.desc, self.params)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            st = L.wdlb_create(C.byref(self.desc), C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
+                               nbytes, C.byref(h))
+            if st != OK:
+                raise WdlbError(st, "wdlb_create")
         self.h = h
         self._L = L
 
