@@ -206,19 +206,21 @@ const char *wdlb_kernel_name(int32_t kernel);
  *         growing shell reach;
  *   3     32 x 16 x 1 nodes, both staged in LDS;
  *   4     16 x 16 x 1 nodes, contact values read through the caches;
- *   5     16 x 16 x 2 nodes, both staged in LDS (lattices at most 16 wide).
+ *   5     16 x 16 x 2 nodes, both staged in LDS (lattices at most 16 wide);
+ *   6     32 x 8 x 2 nodes, (rho, u1) staged in LDS, contact values read
+ *         through the caches.
  * wdlb_set_tile(ctx, -1) (the default) picks variant 5 for lattices at most
- * 16 nodes wide in x when it fits, else the first of 0..4 whose LDS rings
- * fit the shell reach of sigma, and for sigma = 3, 4, 6, 8 or 10 runs
+ * 16 nodes wide in x when it fits; else, in FP32 with a compiled shell
+ * (sigma = 3, 4, 6, 8 or 10), variant 6; else the first of 0..4 whose LDS
+ * rings fit the shell reach of sigma.  For sigma = 3, 4, 6, 8 or 10 it runs
  * kernels compiled for that shell (offsets and weights fixed at compile
- * time) when that variant stages both fields in LDS (variant 5: sigma = 4
- * in FP32).  A variant >= 0 forces that tile with the table-driven kernels
- * and fails with WDLB_E_INVAL, leaving the previous choice, when it does not
- * fit.  wdlb_set_params
- * re-applies the request for the new sigma.  wdlb_get_tile returns the
- * variant in use and (if specialised is not NULL) 1 when the compiled-shell
- * kernels run, else 0. */
-#define WDLB_NTILES 6
+ * time) on variant 6, on variant 5 at sigma = 4 in FP32, and on the chosen
+ * one of 0..3 in FP64.  A variant >= 0 forces that tile with the
+ * table-driven kernels and fails with WDLB_E_INVAL, leaving the previous
+ * choice, when it does not fit.  wdlb_set_params re-applies the request for
+ * the new sigma.  wdlb_get_tile returns the variant in use and (if
+ * specialised is not NULL) 1 when the compiled-shell kernels run, else 0. */
+#define WDLB_NTILES 7
 wdlb_status wdlb_set_tile(wdlb_ctx *ctx, int32_t variant);
 wdlb_status wdlb_get_tile(wdlb_ctx *ctx, int32_t *variant, int32_t *specialised);
 

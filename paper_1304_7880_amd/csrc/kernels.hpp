@@ -1190,6 +1190,42 @@ __device__ __forceinline__ void sh_w(R g, const V4<R> &sv, const V4<R> &c0, R &w
     wz = G * (sv.w - c0.w);
 }
 
+// Buffer descriptors of the four (x, y)-parity sub-lattices of the contact
+// value in the plane z + floor(c/2) (z-parity c & 1), each based at the
+// corner (-O, -O) of the half-reach window, so that every image offset is
+// non-negative.  A raw buffer (stride 0) of num_records bytes; reads past it
+// return 0 (the lattices that use these kernels stay well inside).
+template <typename R>
+__device__ __forceinline__ void gamma_rsrc(const R *__restrict__ gam_p, const Pad &p, int c, int O,
+                                           __amdgpu_buffer_rsrc_t (&gr)[4])
+{
+    const long long zoff = (long long)(c >> 1) * p.PXY - (long long)O * p.PX - O;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R *b = gam_p + (long long)(k + 4 * (c & 1)) * p.NP + zoff;
+        gr[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(b), (short)0, 0x7fffffff, 0x00020000);
+    }
+}
+
+// gamma of the image (sa a, sb b, c) of a compiled quad Q (sa, sb = +-1): from
+// the LDS gamma ring (GL; gc is the ring slice of e_z = c shifted to the
+// corner of the lane's window), or through the vector caches from the padded
+// arrays by a buffer load whose image offset is a scalar (the same for the
+// whole wave) and whose lane offset gvo is the lane's padded index in bytes.
+// Either way no vector instruction forms the address.
+template <typename R, bool GL, int O, int LXg, int LG, int A, int B, int H, int SA, int SB>
+__device__ __forceinline__ R gamma_img(const R *gc, const __amdgpu_buffer_rsrc_t (&gr)[4], int PX, unsigned gvo)
+{
+    constexpr int ox = (SA * A) >> 1, oy = (SB * B) >> 1;
+    if constexpr (GL) {
+        return gc[(H & 3) * LG + (O + ox) + (O + oy) * LXg];
+    } else {
+        static_assert(sizeof(R) == 4, "contact values through buffer loads are FP32");
+        return __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(gr[H & 3], (int)gvo, ((oy + O) * PX + (ox + O)) * 4, 0));
+    }
+}
+
 template <typename R, int S2, int TX, int TY, int TZ, int NR, int NG>
 __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const R *__restrict__ rho_p,
                                                             const R *__restrict__ jx, const R *__restrict__ jy,
@@ -1198,7 +1234,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
                                                             int tiles_z, V4<R> *__restrict__ ru1_p,
                                                             V4<R> *__restrict__ fmf)
 {
-    static_assert(NG > 0, "specialised shell kernels stage gamma in LDS");
+    constexpr bool GL = NG > 0;
     using SH = Shell<S2>;
     constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1210,7 +1246,9 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
     // the node's own inputs of mf_finish, fetched now and pinned after the
     // first c-step so that their latency hides behind it
     const int xc = min(x, g.nx - 1), yc = min(y, g.ny - 1), zc = min(z, g.nz - 1), ic = (zc * g.ny + yc) * g.nx + xc;
-    R rr = rho_p[pidx(p, xc, yc, zc)], jxi = jx[ic], jyi = jy[ic], jzi = jz[ic];
+    const int gbase = pidx(p, xc, yc, zc);
+    const unsigned gvo = (unsigned)gbase * (unsigned)sizeof(R);
+    R rr = rho_p[gbase], jxi = jx[ic], jyi = jy[ic], jzi = jz[ic];
     R fx = 0, fy = 0, fz = 0;
     static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
         constexpr int c = decltype(ci)::value;
@@ -1223,27 +1261,28 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_meanfield_s(Geom g, Pad p, const
         }
         rg.template begin<S>(c, p, rho_p, gam_p);
         const R *pc = rg.plane(c) - (RC + RC * LX);
-        const R *gc = rg.gamma(c) - (O + O * LXg);
+        const R *gc = GL ? rg.gamma(c) - (O + O * LXg) : nullptr;
+        __amdgpu_buffer_rsrc_t gr[4];
+        if constexpr (!GL) gamma_rsrc<R>(gam_p, p, c, O, gr);
         static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
             constexpr CQuad Q = SH::T.q[decltype(qi)::value];
-            constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
-            constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
-                          gnb = (O + ((-b) >> 1)) * LXg;
+            constexpr int a = Q.a, b = Q.b;
+#define WDLB_GAM(SA, SB) gamma_img<R, GL, O, LXg, LG, a, b, Q.h, SA, SB>(gc, gr, p.PX, gvo)
             if constexpr (a == 0 && b == 0) {
                 R G;
                 {
 #pragma clang fp contract(off)
-                    G = gc[hb + ga + gb] * pc[RC + RC * LX];
+                    G = WDLB_GAM(1, 1) * pc[RC + RC * LX];
                 }
                 fz += R(4 * Q.pz) * G;
             } else if constexpr (a == 0) {  // images (0, b) and (0, -b)
-                mf_quad_pair<R>(gc[hb + ga + gb], pc[RC + (RC + b) * LX], gc[hb + ga + gnb], pc[RC + (RC - b) * LX],
+                mf_quad_pair<R>(WDLB_GAM(1, 1), pc[RC + (RC + b) * LX], WDLB_GAM(1, -1), pc[RC + (RC - b) * LX],
                                 R(2 * Q.py), R(2 * Q.pz), fy, fz);
             } else if constexpr (b == 0) {  // images (a, 0) and (-a, 0)
-                mf_quad_pair<R>(gc[hb + ga + gb], pc[(RC + a) + RC * LX], gc[hb + gna + gb], pc[(RC - a) + RC * LX],
+                mf_quad_pair<R>(WDLB_GAM(1, 1), pc[(RC + a) + RC * LX], WDLB_GAM(-1, 1), pc[(RC - a) + RC * LX],
                                 R(2 * Q.px), R(2 * Q.pz), fx, fz);
             } else {
-                const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+                const R gm[4] = {WDLB_GAM(1, 1), WDLB_GAM(-1, 1), WDLB_GAM(1, -1), WDLB_GAM(-1, -1)};
                 const R rm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
                                  pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
                 mf_quad<R>(gm, rm, R(Q.px), R(Q.py), R(Q.pz), fx, fy, fz);
@@ -1265,7 +1304,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
                                                         int tiles_y, int tiles_z, R *__restrict__ Fo,
                                                         R *__restrict__ Ao)
 {
-    static_assert(NG > 0, "specialised shell kernels stage gamma in LDS");
+    constexpr bool GL = NG > 0;
     using SH = Shell<S2>;
     constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1274,7 +1313,9 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     ShellRings<R, V4<R>, TX, TY, TZ, NR, NG> rg;
     rg.init(lds_raw, p, RC, tc, ru1_p, gam_p);
-    const V4<R> c0 = ru1_p[pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1))];
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const unsigned gvo = (unsigned)gbase * (unsigned)sizeof(R);
+    const V4<R> c0 = ru1_p[gbase];
     // F^mf of the node for sh_finish, fetched now, pinned after the first c-step
     V4<R> fm = fmf[(min(z, g.nz - 1) * g.ny + min(y, g.ny - 1)) * g.nx + min(x, g.nx - 1)];
     R acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1288,16 +1329,16 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
         }
         rg.template begin<S>(c, p, ru1_p, gam_p);
         const V4<R> *pc = rg.plane(c) - (RC + RC * LX);
-        const R *gc = rg.gamma(c) - (O + O * LXg);
+        const R *gc = GL ? rg.gamma(c) - (O + O * LXg) : nullptr;
+        __amdgpu_buffer_rsrc_t gr[4];
+        if constexpr (!GL) gamma_rsrc<R>(gam_p, p, c, O, gr);
         static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
             constexpr CQuad Q = SH::T.q[decltype(qi)::value];
-            constexpr int a = Q.a, b = Q.b, hb = (Q.h & 3) * LG;
-            constexpr int ga = O + (a >> 1), gna = O + ((-a) >> 1), gb = (O + (b >> 1)) * LXg,
-                          gnb = (O + ((-b) >> 1)) * LXg;
+            constexpr int a = Q.a, b = Q.b;
             if constexpr (a == 0 && b == 0) {
                 // one image: only the z-even outputs, 4 W, remain
                 R wx, wy, wz;
-                sh_w<R>(gc[hb + ga + gb], pc[RC + RC * LX], c0, wx, wy, wz);
+                sh_w<R>(WDLB_GAM(1, 1), pc[RC + RC * LX], c0, wx, wy, wz);
                 acc[2] += R(4 * Q.qzz) * wz;
                 acc[5] += R(4 * Q.pz) * wz;
                 acc[7] += R(4 * Q.pz) * wx;
@@ -1306,8 +1347,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
                 // images (0, b), (0, -b): the x-odd outputs vanish, the others
                 // are twice the sum (even) or difference (y-odd) of the two
                 R w0x, w0y, w0z, w2x, w2y, w2z, x0h, xYh, y0h, yYh, z0h, zYh;
-                sh_w<R>(gc[hb + ga + gb], pc[RC + (RC + b) * LX], c0, w0x, w0y, w0z);
-                sh_w<R>(gc[hb + ga + gnb], pc[RC + (RC - b) * LX], c0, w2x, w2y, w2z);
+                sh_w<R>(WDLB_GAM(1, 1), pc[RC + (RC + b) * LX], c0, w0x, w0y, w0z);
+                sh_w<R>(WDLB_GAM(1, -1), pc[RC + (RC - b) * LX], c0, w2x, w2y, w2z);
                 {
 #pragma clang fp contract(off)
                     x0h = w0x + w2x;
@@ -1330,8 +1371,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
             } else if constexpr (b == 0) {
                 // images (a, 0), (-a, 0): the y-odd outputs vanish
                 R w0x, w0y, w0z, w1x, w1y, w1z, x0h, xXh, y0h, yXh, z0h, zXh;
-                sh_w<R>(gc[hb + ga + gb], pc[(RC + a) + RC * LX], c0, w0x, w0y, w0z);
-                sh_w<R>(gc[hb + gna + gb], pc[(RC - a) + RC * LX], c0, w1x, w1y, w1z);
+                sh_w<R>(WDLB_GAM(1, 1), pc[(RC + a) + RC * LX], c0, w0x, w0y, w0z);
+                sh_w<R>(WDLB_GAM(-1, 1), pc[(RC - a) + RC * LX], c0, w1x, w1y, w1z);
                 {
 #pragma clang fp contract(off)
                     x0h = w0x + w1x;
@@ -1352,7 +1393,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
                 acc[7] += R(2 * Q.px) * zXh;
                 acc[8] += R(2 * Q.pz) * y0h;
             } else {
-                const R gm[4] = {gc[hb + ga + gb], gc[hb + gna + gb], gc[hb + ga + gnb], gc[hb + gna + gnb]};
+                const R gm[4] = {WDLB_GAM(1, 1), WDLB_GAM(-1, 1), WDLB_GAM(1, -1), WDLB_GAM(-1, -1)};
                 const V4<R> sm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
                                      pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
                 sh_quad<R>(gm, sm, c0, R(Q.px), R(Q.py), R(Q.pz), R(Q.qxx), R(Q.qyy), R(Q.qzz), R(Q.qxy),
@@ -1366,6 +1407,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
     if (!valid) return;
     sh_finish_v<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fm, Fo, Ao);
 }
+#undef WDLB_GAM
 
 // F (3N) and A (xx, yy, zz, xy, xz, yz; 6N) for nonlocal = 0: F = rho g
 template <typename R>

@@ -56,7 +56,8 @@ struct wdlb_ctx {
     int nq, nball, rb, reach;  // quad count; ball size and reach; shell reach
     int dtile;                 // k_density tile (index into DENSITY_TILES)
     double wS;         // 4 pi / |S|
-    int tile;          // contact-shell tile variant (index into SHELL_TILES)
+    int tile;          // contact-shell tile variant of the viscous/SMDB kernel (index into SHELL_TILES)
+    int tile_mf;       // and of the mean-field kernel
     int tile_req;      // requested variant, -1 = automatic
     int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
     int spec_b2;       // 2 sigma of the specialised density kernel in use, 0 = generic
@@ -249,9 +250,17 @@ std::vector<Quad<R>> build_quads(double sigma, int &nshell)
 struct ShellTile {
     int TX, TY, TZ, NR, NG;
 };
-constexpr ShellTile SHELL_TILES[] = {{32, 8, 2, 2, 5}, {32, 8, 2, 3, 6}, {32, 8, 2, 4, 8}, {32, 16, 1, 7, 13},
-                                     {16, 16, 1, 10, 0}, {16, 16, 2, 2, 5}};
+constexpr ShellTile SHELL_TILES[] = {{32, 8, 2, 2, 5},   {32, 8, 2, 3, 6},  {32, 8, 2, 4, 8}, {32, 16, 1, 7, 13},
+                                     {16, 16, 1, 10, 0}, {16, 16, 2, 2, 5}, {32, 8, 2, 4, 0}};
 constexpr int NARROW_TILE = 5;  // the 16 x 16 x 2 variant
+// 32 x 8 x 2 with only the (rho, u1) ring in LDS, gamma read through the
+// vector caches: the LDS then serves the images alone, and a block needs
+// half the LDS (more blocks per CU).  The automatic choice of the viscous /
+// SMDB kernel for wide FP32 lattices with a compiled shell of 2 sigma >=
+// L1G_MIN_S2 (the mean-field kernel, whose quads read four times fewer
+// bytes of images, keeps its gamma ring: through the caches it is slower).
+constexpr int L1G_TILE = 6;
+constexpr int L1G_MIN_S2 = 16;
 constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
 static_assert(NTILES == WDLB_NTILES, "the header's variant count");
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -314,6 +323,7 @@ bool compiled_shell(int s2, int tile, int reach)
 {
     if (s2 == 0) return false;
     if (tile == NARROW_TILE) return std::is_same<R, float>::value && s2 == 8;
+    if (tile == L1G_TILE) return std::is_same<R, float>::value && s2 >= L1G_MIN_S2;
     return tile == pick_tile_wide(reach, sizeof(R)) && SHELL_TILES[tile].NG > 0;
 }
 template <typename R>
@@ -364,10 +374,17 @@ wdlb_status upload_tables(wdlb_ctx *c)
     if (c->tile_req >= 0) {
         if (!tile_fits(SHELL_TILES[c->tile_req], reach, sizeof(R)))
             return fail(c, WDLB_E_INVAL, "the requested shell tile does not fit this sigma");
-        c->tile = c->tile_req;
+        c->tile = c->tile_mf = c->tile_req;
     } else {
-        c->tile = pick_tile(reach, sizeof(R), c->g.nx);
-        if (c->tile >= 0 && compiled_shell<R>(s2c, c->tile, reach)) c->spec_s2 = s2c;
+        c->tile = c->tile_mf = pick_tile(reach, sizeof(R), c->g.nx);
+        // the cache-gamma tile for the viscous/SMDB kernel: its buffer loads
+        // take a lane offset below 2^31 bytes into one padded sub-lattice
+        if (std::is_same<R, float>::value && s2c >= L1G_MIN_S2 && c->tile >= 0 && c->tile != NARROW_TILE &&
+            compiled_shell<R>(s2c, c->tile, reach) && tile_fits(SHELL_TILES[L1G_TILE], reach, sizeof(R)) &&
+            (double)sizeof(R) * (double)c->pad.NP < 2.0e9)
+            c->tile = L1G_TILE;
+        if (c->tile >= 0 && compiled_shell<R>(s2c, c->tile_mf, reach) && compiled_shell<R>(s2c, c->tile, reach))
+            c->spec_s2 = s2c;
         if (compiled_density<R>(s2c, dtile, rb)) c->spec_b2 = s2c;
     }
     if (c->tile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the shell tiles");
@@ -487,41 +504,47 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
     });
 }
 
-// the pair specialised for the shell 2 sigma = S2 on tile TI
-template <typename R, int S2, int TI>
+// the pair specialised for the shell 2 sigma = S2: the mean-field kernel on
+// tile TIM, the viscous/SMDB kernel on tile TIS
+template <typename R, int S2, int TIM, int TIS>
 wdlb_status launch_shell_pair_s(wdlb_ctx *c)
 {
     constexpr int RC = Shell<S2>::R;
-    static_assert(TI >= 0, "no tile for this shell");
-    if (c->tile != TI) return fail(c, WDLB_E_STATE, "compiled shell kernels are for another tile");
-    constexpr ShellTile T = SHELL_TILES[TI];
-    constexpr int TX = T.TX, TY = T.TY, TZ = T.TZ, NR = T.NR, NG = T.NG;
+    static_assert(TIM >= 0 && TIS >= 0, "no tile for this shell");
+    if (c->tile_mf != TIM || c->tile != TIS) return fail(c, WDLB_E_STATE, "compiled shell kernels are for other tiles");
     if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
-    if constexpr (NG == 0) {
-        return launch_shell_pair<R, TX, TY, TZ, NR, NG>(c);
+    if constexpr (SHELL_TILES[TIM].NG == 0 || (TIM != TIS && TIS != L1G_TILE)) {
+        // no compiled kernels on these tiles (the automatic choice never asks)
+        return fail(c, WDLB_E_STATE, "no compiled shell kernels for these tiles");
     } else {
         const Geom g = c->g;
         const wdlb_params &p = c->prm;
         const double s = p.sigma;
-        const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (c->nz_run + TZ - 1) / TZ;
-        const dim3 grid(tx * ty * tz), block(TX * TY * TZ);
-        const size_t lmf = shell_lds_bytes(TX, TY, TZ, RC, sizeof(R), sizeof(R), true);
-        const size_t lsh = shell_lds_bytes(TX, TY, TZ, RC, sizeof(V4<R>), sizeof(R), true);
-        auto kmf = k_meanfield_s<R, S2, TX, TY, TZ, NR, NG>;
-        auto ksh = k_shell_s<R, S2, TX, TY, TZ, NR, NG>;
-        HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
-        HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
-        wdlb_status st = launch(c, K_MEANFIELD, [&] {
-            hipLaunchKernelGGL(kmf, grid, block, lmf, c->stream, g, c->pad, (const R *)c->rho_p, (const R *)c->jx,
-                               (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p, R(-KT * s * s), R(p.g[0]),
-                               R(p.g[1]), R(p.g[2]), tx, ty, tz, (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
-        });
+        wdlb_status st;
+        {
+            constexpr ShellTile T = SHELL_TILES[TIM];
+            const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
+            const size_t lmf = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(R), sizeof(R), true);
+            auto kmf = k_meanfield_s<R, S2, T.TX, T.TY, T.TZ, T.NR, T.NG>;
+            HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
+            st = launch(c, K_MEANFIELD, [&] {
+                hipLaunchKernelGGL(kmf, dim3(tx * ty * tz), dim3(T.TX * T.TY * T.TZ), lmf, c->stream, g, c->pad,
+                                   (const R *)c->rho_p, (const R *)c->jx, (const R *)c->jy, (const R *)c->jz,
+                                   (const R *)c->gam_p, R(-KT * s * s), R(p.g[0]), R(p.g[1]), R(p.g[2]), tx, ty, tz,
+                                   (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
+            });
+        }
         if (st != WDLB_OK) return st;
+        constexpr ShellTile T = SHELL_TILES[TIS];
+        const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
+        const size_t lsh = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(V4<R>), sizeof(R), T.NG > 0);
+        auto ksh = k_shell_s<R, S2, T.TX, T.TY, T.TZ, T.NR, T.NG>;
+        HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
         return launch(c, K_SHELL, [&] {
-            hipLaunchKernelGGL(ksh, grid, block, lsh, c->stream, g, c->pad, (const V4<R> *)c->ru1_p,
-                               (const R *)c->gam_p, (const V4<R> *)c->fmf, R(2.0 * s * s * std::sqrt(KT / M_PI)),
-                               R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]), R(p.g[2]), p.smdb, tx, ty, tz,
-                               (R *)c->F, (R *)c->A);
+            hipLaunchKernelGGL(ksh, dim3(tx * ty * tz), dim3(T.TX * T.TY * T.TZ), lsh, c->stream, g, c->pad,
+                               (const V4<R> *)c->ru1_p, (const R *)c->gam_p, (const V4<R> *)c->fmf,
+                               R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]),
+                               R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A);
         });
     }
 }
@@ -529,10 +552,21 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
 template <typename R>
 wdlb_status launch_shells(wdlb_ctx *c)
 {
-#define WDLB_WIDE(S2) launch_shell_pair_s<R, S2, pick_tile_wide(Shell<S2>::R, sizeof(R))>(c)
+#define WDLB_TW(S2) pick_tile_wide(Shell<S2>::R, sizeof(R))
+#define WDLB_WIDE(S2) launch_shell_pair_s<R, S2, WDLB_TW(S2), WDLB_TW(S2)>(c)
     if (c->spec_s2 > 0) {
-        if constexpr (std::is_same<R, float>::value)
-            if (c->tile == NARROW_TILE && c->spec_s2 == 8) return launch_shell_pair_s<R, 8, NARROW_TILE>(c);
+        if constexpr (std::is_same<R, float>::value) {
+            if (c->tile == NARROW_TILE && c->spec_s2 == 8)
+                return launch_shell_pair_s<R, 8, NARROW_TILE, NARROW_TILE>(c);
+            if (c->tile == L1G_TILE) {
+                static_assert(L1G_MIN_S2 == 16, "one case per shell that uses the cache-gamma tile");
+                switch (c->spec_s2) {
+                case 16: return launch_shell_pair_s<R, 16, WDLB_TW(16), L1G_TILE>(c);
+                case 20: return launch_shell_pair_s<R, 20, WDLB_TW(20), L1G_TILE>(c);
+                default: break;
+                }
+            }
+        }
         switch (c->spec_s2) {
         case 6: return WDLB_WIDE(6);
         case 8: return WDLB_WIDE(8);
@@ -543,14 +577,16 @@ wdlb_status launch_shells(wdlb_ctx *c)
         }
     }
 #undef WDLB_WIDE
-    static_assert(NTILES == 6, "one case per entry of SHELL_TILES");
+#undef WDLB_TW
+    static_assert(NTILES == 7, "one case per entry of SHELL_TILES");
     switch (c->tile) {
     case 0: return launch_shell_pair<R, 32, 8, 2, 2, 5>(c);
     case 1: return launch_shell_pair<R, 32, 8, 2, 3, 6>(c);
     case 2: return launch_shell_pair<R, 32, 8, 2, 4, 8>(c);
     case 3: return launch_shell_pair<R, 32, 16, 1, 7, 13>(c);
     case 4: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
-    default: return launch_shell_pair<R, 16, 16, 2, 2, 5>(c);
+    case 5: return launch_shell_pair<R, 16, 16, 2, 2, 5>(c);
+    default: return launch_shell_pair<R, 32, 8, 2, 4, 0>(c);
     }
 }
 

@@ -19,7 +19,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_NOT_CONVERGED = range(7)
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSTABLE", 5: "E_STATE", 6: "E_NOT_CONVERGED"}
 FP64, FP32, BF16_NEQ, FP32_LOCAL64, BF16_NEQ_LOCAL64 = 0, 1, 2, 3, 4
 NKERNELS = 5
-NTILES = 6
+NTILES = 7
 PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ, "fp32_local64": FP32_LOCAL64,
              "bf16_local64": BF16_NEQ_LOCAL64}
 

@@ -88,11 +88,12 @@ def test_random_fields_few_steps(case, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(7))
 def test_shell_tile_variants(variant, prec, tol):
     """Every contact-shell tile variant (LDS rings of 32x8x2, 32x16x1 and
-    16x16x2, and the 16x16x1 tile reading gamma through the caches), forced
-    on a walled 40x20x13 lattice that leaves ragged tiles in x, y and z."""
+    16x16x2, and the 16x16x1 and 32x8x2 tiles reading gamma through the
+    caches), forced on a walled 40x20x13 lattice that leaves ragged tiles in
+    x, y and z."""
     from paper_1304_7880_amd import wdlb
     nx, ny, nz, sigma, eta, tau, g = 40, 20, 13, 4.0, 0.3, 0.9, (1e-4, -3e-5, 0.0)
     _say(f"tile variant {variant} {prec}")
