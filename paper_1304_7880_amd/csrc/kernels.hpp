@@ -541,6 +541,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density(Geom g, Pad p, int rb, c
     density_gamma<R, TX, TY>(g, p, x, y, z, nb + (tc.lz * MY + tc.ly) * MX + tc.lx, eta_per_n, wS, gam_p, flag);
 }
 
+// the union table of the ball's column of MZ points, as a constant
+template <int S2, int MZ>
+struct Column {
+    static constexpr BallColumn<S2, MZ> T{};
+};
+
 // specialised for the ball of 2 sigma = S2: offsets are LDS immediates, the
 // sum runs in 8 interleaved partial sums
 template <typename R, int S2, int TX, int TY, int TZ>
@@ -559,20 +565,53 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_density_s(Geom g, Pad p, const R
     int *zfl = reinterpret_cast<int *>(nb + MN);
     density_fill<R, NT, TZ>(g, tc, p, rb, LX, LY, LZ, rho_p, win, zfl);
     __syncthreads();
-    auto nbar_at = [&](int mx, int my, int mz) __attribute__((always_inline)) {
-        R v = 0;
-        if (zfl[mz]) {
-            const R *c = win + mz * LXY + my * LX + mx;  // corner of the lane's ball window
-            R s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            static_for<0, B::NB>([&](auto ki) __attribute__((always_inline)) {
-                constexpr int k = decltype(ki)::value;
-                s[k & 7] += c[(B::T.z[k] + rb) * LXY + (B::T.y[k] + rb) * LX + (B::T.x[k] + rb)];
+    // a lane forms nbar for the column (mx, my) of all MZ planes: the union
+    // of the MZ stacked balls is read once, each value added into the
+    // partial sums of every point whose ball holds it; a point's terms
+    // arrive in its ball order, into sum k mod 8, as in the one-point sum
+    using BC = BallColumn<S2, MZ>;
+    static_assert(BC::NU > 0, "ball column table");
+    auto nbar_col = [&](int mx, int my) __attribute__((always_inline)) {
+        const R *c = win + my * LX + mx;  // corner of the ball window of the column's lowest point
+        R s[MZ][8];
+#pragma unroll
+        for (int j = 0; j < MZ; ++j)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) s[j][m] = R(0);
+        static_for<0, BC::NU>([&](auto ui) __attribute__((always_inline)) {
+            constexpr int u = decltype(ui)::value;
+            using CT = Column<S2, MZ>;
+            // one window row (z, y) at a time: the sums of a row are finished
+            // and no load is hoisted above the start of its row, which bounds
+            // the values in flight
+            if constexpr (u > 0 && (CT::T.z[u] != CT::T.z[u - 1] || CT::T.y[u] != CT::T.y[u - 1])) {
+#pragma unroll
+                for (int j = 0; j < MZ; ++j)
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) pin(s[j][m]);
+                asm volatile("" ::: "memory");
+            }
+            const R v = c[(CT::T.z[u] + rb) * LXY + (CT::T.y[u] + rb) * LX + (CT::T.x[u] + rb)];
+            static_for<0, MZ>([&](auto ji) __attribute__((always_inline)) {
+                constexpr int j = decltype(ji)::value;
+                constexpr int k = CT::T.k[u][j];
+                if constexpr (k >= 0) s[j][k & 7] += v;
             });
-            v = (((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]))) * inv_nball;
+        });
+#pragma unroll
+        for (int j = 0; j < MZ; ++j) {
+            const R v = zfl[j] ? (((s[j][0] + s[j][1]) + (s[j][2] + s[j][3])) +
+                                  ((s[j][4] + s[j][5]) + (s[j][6] + s[j][7]))) * inv_nball
+                               : R(0);
+            nb[(j * MY + my) * MX + mx] = v;
         }
-        nb[(mz * MY + my) * MX + mx] = v;
     };
-    density_nbar_sweep<TX, TY, TZ>(nbar_at);
+    // the tile's TX columns first (lanes of a half-wave on one window row:
+    // no bank conflicts), then the extra column mx = TX
+    for (int e = threadIdx.x; e < TX * MY + MY; e += NT) {
+        if (e < TX * MY) nbar_col(e % TX, e / TX);
+        else nbar_col(TX, e - TX * MY);
+    }
     __syncthreads();
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;

@@ -173,4 +173,63 @@ struct Ball {
     static constexpr int NB = BallTable<S2>::NB;
 };
 
+// The balls of MZ points stacked in z (point j at z = j) read together: every
+// lattice offset (x, y, z) of their union once, in the order z, then y, then
+// x, with the ball index k[j] it has for point j (its offset from that point
+// is (x, y, z - j); -1 when outside that ball).  For each point the terms
+// then arrive in its own ball order.
+constexpr int ball_union_size2(int s2, int mz)
+{
+    const int rb = ball_reach2(s2);
+    int n = 0;
+    for (int z = -rb; z <= rb + mz - 1; ++z)
+        for (int y = -rb; y <= rb; ++y)
+            for (int x = -rb; x <= rb; ++x) {
+                bool any = false;
+                for (int j = 0; j < mz; ++j) {
+                    const int zz = z - j;
+                    any = any || 16 * (x * x + y * y + zz * zz) <= s2 * s2;
+                }
+                n += any ? 1 : 0;
+            }
+    return n;
+}
+
+template <int S2, int MZ>
+struct BallColumn {
+    static constexpr int NU = ball_union_size2(S2, MZ);
+    int x[NU], y[NU], z[NU], k[NU][MZ];
+    constexpr BallColumn() : x{}, y{}, z{}, k{}
+    {
+        const int rb = ball_reach2(S2), W = 2 * rb + 1;
+        // ball index of each offset of the reach cube, in the ball's own order
+        static_assert(ball_reach2(S2) <= 8, "ball reach of the index grid");
+        int grid[17 * 17 * 17] = {};
+        int idx = 0;
+        for (int c = -rb; c <= rb; ++c)
+            for (int b = -rb; b <= rb; ++b)
+                for (int a = -rb; a <= rb; ++a)
+                    grid[((c + rb) * W + (b + rb)) * W + (a + rb)] =
+                        16 * (a * a + b * b + c * c) <= S2 * S2 ? idx++ : -1;
+        int n = 0;
+        for (int zz = -rb; zz <= rb + MZ - 1; ++zz)
+            for (int yy = -rb; yy <= rb; ++yy)
+                for (int xx = -rb; xx <= rb; ++xx) {
+                    bool any = false;
+                    int kk[MZ] = {};
+                    for (int j = 0; j < MZ; ++j) {
+                        const int zj = zz - j;
+                        kk[j] = (zj < -rb || zj > rb) ? -1 : grid[((zj + rb) * W + (yy + rb)) * W + (xx + rb)];
+                        any = any || kk[j] >= 0;
+                    }
+                    if (!any) continue;
+                    x[n] = xx;
+                    y[n] = yy;
+                    z[n] = zz;
+                    for (int j = 0; j < MZ; ++j) k[n][j] = kk[j];
+                    ++n;
+                }
+    }
+};
+
 }  // namespace wdlb
