@@ -144,3 +144,51 @@ def test_slab64_full_length_against_column_oracle(prec, tol):
     _say(f"  u_x(z) rel {e_u:.3e}  J rel {e_J:.3e}")
     assert e_u < tol
     assert e_J < tol
+
+
+@pytest.mark.parametrize("prec,tol,ckpts", [("fp64", 1e-10, (100, 500)), ("fp32_local64", 1e-5, (100, 500, 1000, 2000)),
+                                            ("fp32", 1e-4, (100, 500, 1000, 2000))])
+def test_slab64_same_input_3d_oracle(prec, tol, ckpts):
+    """The benchmark slit (64^3, sigma = 6, eta = 0.35, tau = 0.8, seeded +-1 %
+    density noise) against the FP64 3-D oracle run on the same seeded input
+    (tests/golden/make_slab64_3d_ref.py): at each stored step the plane
+    means n(z), u_x(z), the pore flux, the mean velocity and the mass, and
+    density and velocity at a few single nodes (walls, mid-pore, ragged tile
+    positions), where the noise-driven flow is still three-dimensional."""
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import SLAB_64
+    ref = _golden("slab64_3d_oracle.json")
+    w = SLAB_64
+    assert (w.nx, w.ny, w.nz, w.sigma, w.eta, w.tau, w.noise, w.seed) == (
+        ref["nx"], ref["ny"], ref["nz"], ref["sigma"], ref["eta"], ref["tau"], ref["noise"], ref["seed"])
+    _say(f"slab {w.name} {prec} against the 3-D oracle at steps {ckpts}")
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, True, prec, w.sigma, w.eta, w.tau, w.g)
+    n, u = initial_fields(w)
+    ctx.init_fields(n, u)
+    done = 0
+    by_step = {c["steps"]: c for c in ref["checkpoints"]}
+    for t in ckpts:
+        ctx.step(t - done)
+        done = t
+        o = by_step[t]
+        n_g, ux_g = ctx.read_profiles()
+        J_g, U_g, M_g = ctx.read_flux()
+        rho_g, u_g = ctx.read_fields()
+        ux_o = np.array(o["ux_z"])
+        e_u = float(np.abs(ux_g - ux_o).max() / np.abs(ux_o).max())
+        e_n = float(np.abs(n_g - np.array(o["n_z"])).max() / np.abs(o["n_z"]).max())
+        e_J = abs(J_g - o["j_pore"]) / abs(o["j_pore"])
+        e_U = abs(U_g - o["u_pore"]) / abs(o["u_pore"])
+        e_M = abs(M_g - o["mass"]) / o["mass"]
+        pr_o = np.array(o["probe_rho_u"])
+        pr_g = np.array([[rho_g[i], u_g[i], u_g[w.N + i], u_g[2 * w.N + i]]
+                         for i in ((z * w.ny + y) * w.nx + x for x, y, z in ref["probes"])])
+        e_pr = float(np.abs(pr_g[:, 0] - pr_o[:, 0]).max() / np.abs(pr_o[:, 0]).max())
+        e_pu = float(np.abs(pr_g[:, 1:] - pr_o[:, 1:]).max() / np.abs(pr_o[:, 1:]).max())
+        _say(f"  step {t}: u_x(z) {e_u:.2e} n(z) {e_n:.2e} J {e_J:.2e} u_pore {e_U:.2e} mass {e_M:.2e} "
+             f"node rho {e_pr:.2e} node u {e_pu:.2e}")
+        assert e_u < tol and e_J < tol and e_U < tol, t
+        assert e_n < tol and e_pr < tol, t
+        assert e_M < (1e-13 if prec == "fp64" else 1e-6), t
+        assert e_pu < 10 * tol, t
+    ctx.destroy()
