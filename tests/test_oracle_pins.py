@@ -381,3 +381,50 @@ def test_column_equals_3d(walls, sigma, eta, tau, g, steps):
     assert np.abs(u3.reshape(3, nz, 12)[:, :, 5] - u1).max() < 1e-12 * 1e-3
     Ascale = (KT / 5) * sigma ** 2 * n0 * n0 * 4 * math.pi * g_cs(eta) * 1e-3
     assert np.abs(A3.reshape(3, 3, nz, 12)[..., 7] - A1).max() < 1e-12 * Ascale
+
+
+# --------------------------------------------------------------------------
+# Stability of the explicit viscous update (Sec. 5: the fields of step 2 are
+# formed from the current fields and applied in one explicit step).  Per
+# step the viscous force changes a longitudinal velocity mode u_z ~ cos(qz)
+# of the uniform fluid by the factor 1 + lambda(q),
+#   lambda(q) = -2 sigma^2 sqrt(kT/pi) wS g0 n0 sum_e kz^2 (1 - cos(q e_z)),
+# so the explicit scheme is unstable once min_q lambda < -2.  The lattice
+# sum puts that bound at eta = 0.326 for sigma = 4 (the minimum lies at
+# q sigma ~ 3.8, not at the checkerboard q = pi).  The column oracle, from a
+# uniform fluid with 1e-6 density noise, must stay quiet just below the
+# bound and break down just above it.
+# --------------------------------------------------------------------------
+def _viscous_lambda_min(sigma, eta):
+    e = ref.shell(sigma).astype(np.float64)
+    k = e / np.linalg.norm(e, axis=1)[:, None]
+    wS = 4 * math.pi / len(e)
+    n0 = packing_to_density(eta, sigma)
+    cv = 2 * sigma ** 2 * math.sqrt(KT / math.pi)
+    qs = np.linspace(0.01, math.pi, 400)
+    return min(-cv * wS * g_cs(eta) * n0 * float((k[:, 2] ** 2 * (1 - np.cos(q * e[:, 2]))).sum()) for q in qs)
+
+
+def _column_breaks(sigma, eta, steps, L=64):
+    col = Column(L, sigma, 1.0, walls=False)
+    n0 = packing_to_density(eta, sigma)
+    rng = np.random.default_rng(3)
+    col.init(n0 * (1 + 1e-6 * rng.uniform(-1, 1, L)), np.zeros((3, L)))
+    try:
+        col.step(steps)
+        rho = col.fields()[0]
+    except FloatingPointError:
+        return True
+    return bool(np.abs(rho / n0 - 1).max() > 1e-3)
+
+
+def test_explicit_viscous_stability_bound():
+    sigma = 4.0
+    lo, hi = 0.2, 0.45
+    for _ in range(40):   # bisect lambda_min(eta) = -2
+        mid = 0.5 * (lo + hi)
+        lo, hi = (lo, mid) if _viscous_lambda_min(sigma, mid) < -2 else (mid, hi)
+    eta_c = 0.5 * (lo + hi)
+    assert 0.32 < eta_c < 0.33
+    assert not _column_breaks(sigma, eta_c - 0.006, 3000)
+    assert _column_breaks(sigma, eta_c + 0.006, 3000)
