@@ -56,6 +56,7 @@ def lib():
         L.wdlb_ref_meanfield.argtypes = [cp, dp, dp, dp]
         L.wdlb_ref_viscous.argtypes = [cp, dp, dp, dp, dp, dp]
         L.wdlb_ref_fields.argtypes = [cp, dp, dp, dp, dp, dp, C.c_void_p]
+        L.wdlb_ref_thermal.argtypes = [cp, dp, dp, dp, dp, dp, dp, dp]
         L.wdlb_ref_init.argtypes = [cp, dp, dp, dp]
         L.wdlb_ref_step.argtypes = [cp, dp, C.c_int64]
         L.wdlb_ref_reduce.argtypes = [cp, dp, dp, dp, dp, dp]
@@ -215,3 +216,14 @@ def viscous(cfg: Config, rho, nb, v):
     a = lambda x: np.ascontiguousarray(x, dtype=np.float64).ravel()
     _check(lib().wdlb_ref_viscous(C.byref(c), a(rho), a(nb), a(v), Fv, A), "viscous")
     return Fv, A
+
+
+def thermal(cfg: Config, rho, nb, v, T):
+    """(Q[N], B[3N], F^T[3N]) of the fields rho, v (3N), T (N) (Sec. 3, eqs.
+    campob1, campos, thermalforce; k_B = m = 1)."""
+    N = cfg.N
+    Q, B, FT = np.zeros(N), np.zeros(3 * N), np.zeros(3 * N)
+    c = cfg.c()
+    a = lambda x: np.ascontiguousarray(x, dtype=np.float64).ravel()
+    _check(lib().wdlb_ref_thermal(C.byref(c), a(rho), a(nb), a(v), a(T), Q, B, FT), "thermal")
+    return Q, B, FT

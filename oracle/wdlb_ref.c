@@ -403,6 +403,67 @@ int wdlb_ref_viscous(const wdlb_ref_cfg *c, const double *rho, const double *nba
     return bad ? REF_EUNSTABLE : REF_OK;
 }
 
+/* Thermal fields (Sec. 3; the isothermal step of Sec. 5 uses none of them),
+ * for given fields n (rho), v and T with k_B = m = 1, at each node r:
+ *   Q(r)   = n(r) sigma^2 sum_e G(r,e) [ -T(r) (k.dv)/2 + sqrt(T(r)/pi) dT ]
+ *                                                          (eq. campob1)
+ *   B_i(r) = -2 T(r) n(r) sigma^2 sum_e k_i G(r,e) dT        (eq. campos)
+ *   F^T_i(r) = -(sigma^2/2) sum_e k_i G(r,e) dT              (eq. thermalforce)
+ * with k = e/|e|, dv = v(r+e) - v(r), dT = T(r+e) - T(r) and G the shell
+ * weight of O3 (contact value at the midpoint, rho(r+e)), the k_B T factor
+ * of eq. campob1 cancelling the 1/T of its temperature term.  Pairs {e, -e}
+ * are summed first, as in O3a, so uniform v and T give exactly zero.
+ * Outputs Q (N), B (3N), FT (3N); nbar from wdlb_ref_nbar. */
+int wdlb_ref_thermal(const wdlb_ref_cfg *c, const double *rho, const double *nbar, const double *v,
+                     const double *T, double *Q, double *B, double *FT)
+{
+    if (!cfg_ok(c) || c->sigma < 1.0) return REF_EINVAL;
+    long N = nnodes(c);
+    int ns;
+    int32_t *e = shell_table(c, &ns);
+    if (!e) return REF_ENOMEM;
+    double wS = 4.0 * M_PI / ns, s2 = c->sigma * c->sigma;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int z = 0; z < c->nz; ++z)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                long r = site(c, x, y, z);
+                double Tr = T[r];
+                double acc[5] = {0};   /* sum G k dT (3), sum G dT, sum G k.dv */
+                for (int q = 0; q < ns; ++q) {
+                    const int32_t *ep = e + 3 * q;
+                    if (!positive(ep)) continue;
+                    double term[2][5];
+                    for (int side = 0; side < 2; ++side) {
+                        int32_t ee[3] = {side ? -ep[0] : ep[0], side ? -ep[1] : ep[1], side ? -ep[2] : ep[2]};
+                        long s;
+                        double G;
+                        int ok = shell_weight(c, rho, nbar, wS, x, y, z, ee, &s, &G);
+                        for (int t = 0; t < 5; ++t) term[side][t] = 0.0;
+                        if (ok < 0) { bad = 1; continue; }
+                        if (ok == 0) continue;
+                        double len = sqrt((double)(ee[0] * ee[0] + ee[1] * ee[1] + ee[2] * ee[2]));
+                        double k[3] = {ee[0] / len, ee[1] / len, ee[2] / len};
+                        double dT = T[s] - Tr, kdv = 0.0;
+                        for (int d = 0; d < 3; ++d) kdv += k[d] * (v[(long)d * N + s] - v[(long)d * N + r]);
+                        for (int i = 0; i < 3; ++i) term[side][i] = k[i] * G * dT;
+                        term[side][3] = G * dT;
+                        term[side][4] = G * kdv;
+                    }
+                    for (int t = 0; t < 5; ++t) acc[t] += term[0][t] + term[1][t];
+                }
+                double nr = rho[r];
+                Q[r] = nr * s2 * (-0.5 * Tr * acc[4] + sqrt(Tr / M_PI) * acc[3]);
+                for (int i = 0; i < 3; ++i) {
+                    B[(long)i * N + r] = -2.0 * Tr * nr * s2 * acc[i];
+                    FT[(long)i * N + r] = -0.5 * s2 * acc[i];
+                }
+            }
+    free(e);
+    return bad ? REF_EUNSTABLE : REF_OK;
+}
+
 /* O1-O4: the fields at the current time (Sec. 5, steps 2 and 4).
  *   u1 = j/rho + (g + F^mf)/2   velocity of the current populations with the
  *                               half-step forcing of every force but F^v;

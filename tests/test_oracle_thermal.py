@@ -1,0 +1,180 @@
+"""Pins of the oracle's thermal fields (Sec. 3: the energy source Q of eq.
+campob1, the heat-flux correction B_i of eq. campos, the thermal force F^T of
+eq. thermalforce; k_B = m = 1) against what the paper and the mathematics fix.
+
+- At uniform density the contact value is the same at every midpoint, so for
+  T = T0 (1 + eps sin qz) and a velocity u_z = U sin qz the shell sums reduce
+  to closed forms in the lattice sums S1(q) = sum_e k_z sin(q e_z) and
+  C1(q) = sum_e (cos(q e_z) - 1): exact (F^T is linear in T; Q and B carry
+  the local T as a prefactor, which the closed form keeps).  The bar,
+  1e-10 of the largest value, is the rounding of T ~ 1/3 in differences of
+  a thousandth of it, summed over the shell.
+- Their long-wave limits are the Sec. 4 small-gradient results: the
+  heat-flux correction B / (4 omega0) of eq. c1exp22, the collisional
+  conductivity (2/3) sqrt(pi T) g n^2 sigma^4 of eq. thermalcond, the
+  collisional compression work -P^c div u of the energy balance (Sec. 2),
+  and the thermal part of the collisional pressure gradient,
+  F^T = -(1/n) dP^c/dT grad T, with P^c = (2 pi/3) n^2 sigma^3 g T.  The
+  lattice shell carries its mean radius into these (<|e|>/sigma and
+  <|e|^2>/sigma^2, a few per cent).
+- A naive independent evaluation on tiny grids (every displacement of a cube
+  tested against the shell radius directly) equals the oracle to round-off.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1304_7880_amd.workloads import packing_to_density
+
+
+def g_cs(eta):
+    return (1 - eta / 2) / (1 - eta) ** 3
+
+
+def _shell_sums(sigma, q):
+    e = ref.shell(sigma).astype(np.float64)
+    k = e / np.linalg.norm(e, axis=1)[:, None]
+    S1 = float((k[:, 2] * np.sin(q * e[:, 2])).sum())
+    C1 = float((np.cos(q * e[:, 2]) - 1).sum())
+    return len(e), S1, C1, float(np.linalg.norm(e, axis=1).mean()), float((np.linalg.norm(e, axis=1) ** 2).mean())
+
+
+def _wave(sigma, eta, L, eps=0.0, U=0.0, modes=1):
+    cfg = ref.Config(4, 4, L, False, sigma, 1.0)
+    N = cfg.N
+    z = np.repeat(np.arange(L), 16).astype(np.float64)
+    q = 2 * math.pi * modes / L
+    n0 = packing_to_density(eta, sigma)
+    T0 = 1.0 / 3.0
+    rho = np.full(N, n0)
+    T = T0 * (1 + eps * np.sin(q * z))
+    v = np.zeros((3, N))
+    v[2] = U * np.sin(q * z)
+    nb = ref.nbar(cfg, rho)
+    Q, B, FT = ref.thermal(cfg, rho, nb, v.ravel(), T)
+    return cfg, q, z, n0, T0, T, Q, B.reshape(3, N), FT.reshape(3, N)
+
+
+def test_uniform_fields_give_zero():
+    cfg = ref.Config(6, 5, 7, True, 3.0, 1.0)
+    rng = np.random.default_rng(5)
+    rho = packing_to_density(0.3, 3.0) * (1 + 0.2 * rng.uniform(-1, 1, cfg.N))
+    nb = ref.nbar(cfg, rho)
+    Q, B, FT = ref.thermal(cfg, rho, nb, np.tile([1e-3, -2e-3, 5e-4], (cfg.N, 1)).T.ravel(), np.full(cfg.N, 0.4))
+    assert np.abs(Q).max() == 0 and np.abs(B).max() == 0 and np.abs(FT).max() == 0
+
+
+@pytest.mark.parametrize("sigma,eta", [(4.0, 0.2), (6.0, 0.35)])
+def test_temperature_wave_closed_form(sigma, eta):
+    L, eps = 48, 1e-3
+    cfg, q, z, n0, T0, T, Q, B, FT = _wave(sigma, eta, L, eps=eps)
+    nS, S1, C1, _, _ = _shell_sums(sigma, q)
+    G = 4 * math.pi / nS * g_cs(eta) * n0
+    FTz = -0.5 * sigma ** 2 * G * T0 * eps * S1 * np.cos(q * z)
+    assert np.abs(FT[2] - FTz).max() < 1e-10 * np.abs(FTz).max()
+    assert np.abs(FT[:2]).max() < 1e-10 * np.abs(FTz).max()
+    Bz = -2 * T * n0 * sigma ** 2 * G * T0 * eps * S1 * np.cos(q * z)
+    assert np.abs(B[2] - Bz).max() < 1e-10 * np.abs(Bz).max()
+    Qz = n0 * sigma ** 2 * G * np.sqrt(T / math.pi) * T0 * eps * C1 * np.sin(q * z)
+    assert np.abs(Q - Qz).max() < 1e-10 * np.abs(Qz).max()
+
+
+def test_velocity_wave_compression_work():
+    sigma, eta, L, U = 4.0, 0.25, 48, 1e-4
+    cfg, q, z, n0, T0, T, Q, B, FT = _wave(sigma, eta, L, U=U)
+    nS, S1, _, _, _ = _shell_sums(sigma, q)
+    G = 4 * math.pi / nS * g_cs(eta) * n0
+    Qz = -0.5 * n0 * sigma ** 2 * T0 * G * U * S1 * np.cos(q * z)
+    assert np.abs(Q - Qz).max() < 1e-10 * np.abs(Qz).max()
+    assert np.abs(B).max() == 0 and np.abs(FT).max() == 0
+
+
+def _amp(f, q, z, phase):
+    """Amplitude of the cos (phase 0) or sin (phase 1) harmonic of wavenumber q."""
+    b = np.cos(q * z) if phase == 0 else np.sin(q * z)
+    return float((f * b).sum() / (b * b).sum())
+
+
+def test_long_wave_limits_are_the_small_gradient_results():
+    """Sec. 4 and the collisional pressure: at two long waves (q sigma = 0.196
+    and 0.098) the ratio of each field's harmonic to its small-gradient value
+    is 1 + c q^2 + O(q^4); the extrapolation to q = 0 is 1 within 2e-4, and
+    the longer wave alone is within 3e-3."""
+    sigma, eta, eps, U = 4.0, 0.25, 1e-4, 1e-5
+    g = g_cs(eta)
+    ratios = []
+    for L in (128, 256):
+        cfg, q, z, n0, T0, T, Q, B, FT = _wave(sigma, eta, L, eps=eps)
+        _, _, _, emean, e2mean = _shell_sums(sigma, q)
+        r1, r2 = emean / sigma, e2mean / sigma ** 2
+        # heat-flux correction B/(4 omega0) = -(1/omega0) T n^2 g (4 pi/6) sigma^3 dT/dz (eq. c1exp22),
+        # dT/dz = T0 eps q cos(qz)
+        b = -4 * T0 * n0 ** 2 * g * (4 * math.pi / 6) * sigma ** 3 * T0 * eps * q * r1
+        # collisional conduction Q = lambda_c d2T/dz2, lambda_c = (2/3) sqrt(pi T) g n^2 sigma^4 (eq. thermalcond),
+        # d2T/dz2 = -T0 eps q^2 sin(qz)
+        lam_c = 2.0 / 3.0 * math.sqrt(math.pi * T0) * g * n0 ** 2 * sigma ** 4
+        qa = -lam_c * T0 * eps * q * q * r2
+        # thermal force -(1/n) dP^c/dT grad T with P^c = (2 pi/3) n^2 sigma^3 g T
+        f = -(2 * math.pi / 3) * n0 * sigma ** 3 * g * T0 * eps * q * r1
+        # compression work -P^c du_z/dz for u_z = U sin(qz)
+        _, _, _, _, _, _, Qv, _, _ = _wave(sigma, eta, L, U=U)
+        w = -(2 * math.pi / 3) * n0 ** 2 * sigma ** 3 * g * T0 * U * q * r1
+        ratios.append((q, np.array([_amp(B[2], q, z, 0) / b, _amp(Q, q, z, 1) / qa,
+                                    _amp(FT[2], q, z, 0) / f, _amp(Qv, q, z, 0) / w])))
+    (q1, r1_), (q2, r2_) = ratios
+    r0 = (q1 ** 2 * r2_ - q2 ** 2 * r1_) / (q1 ** 2 - q2 ** 2)
+    assert np.abs(r2_ - 1).max() < 3e-3, r2_
+    assert np.abs(r0 - 1).max() < 2e-4, r0
+
+
+def _node(cfg, p):
+    x, y, z = int(p[0]) % cfg.nx, int(p[1]) % cfg.ny, int(p[2])
+    if cfg.walls_z:
+        if z < 0 or z >= cfg.nz:
+            return None
+    else:
+        z %= cfg.nz
+    return (z * cfg.ny + y) * cfg.nx + x
+
+
+@pytest.mark.parametrize("walls,sigma,shape", [(True, 3.0, (5, 4, 6)), (False, 2.0, (4, 5, 3))])
+def test_thermal_fields_brute_force(walls, sigma, shape):
+    nx, ny, nz = shape
+    cfg = ref.Config(nx, ny, nz, walls, sigma, 1.0)
+    rng = np.random.default_rng(17)
+    N = cfg.N
+    n0 = packing_to_density(0.25, sigma)
+    rho = n0 * (1 + 0.3 * rng.uniform(-1, 1, N))
+    v = 0.01 * rng.uniform(-1, 1, (3, N))
+    T = (1.0 / 3.0) * (1 + 0.2 * rng.uniform(-1, 1, N))
+    Q_o, B_o, FT_o = ref.thermal(cfg, rho, ref.nbar(cfg, rho), v.ravel(), T)
+    R = int(math.ceil(sigma + 0.5)) + 1
+    cube = [np.array((dx, dy, dz)) for dz in range(-R, R + 1) for dy in range(-R, R + 1) for dx in range(-R, R + 1)]
+    ball = [d for d in cube if 4 * d.dot(d) <= sigma * sigma]
+    shell = [d for d in cube if (sigma - 0.5) ** 2 <= d.dot(d) < (sigma + 0.5) ** 2]
+    coords = [np.array((i % nx, (i // nx) % ny, i // (nx * ny))) for i in range(N)]
+    nbar = np.array([sum(rho[t] for t in (_node(cfg, r + d) for d in ball) if t is not None) / len(ball)
+                     for r in coords])
+    wS = 4 * math.pi / len(shell)
+    Q, B, FT = np.zeros(N), np.zeros((3, N)), np.zeros((3, N))
+    for i, r in enumerate(coords):
+        for d in shell:
+            t = _node(cfg, r + d)
+            if t is None:
+                continue
+            p = r + d / 2.0
+            corners = [np.array((cx, cy, cz)) for cz in sorted({math.floor(p[2]), math.ceil(p[2])})
+                       for cy in sorted({math.floor(p[1]), math.ceil(p[1])})
+                       for cx in sorted({math.floor(p[0]), math.ceil(p[0])})]
+            nm = np.mean([nbar[_node(cfg, c)] for c in corners])
+            G = wS * g_cs(math.pi * sigma ** 3 * nm / 6) * rho[t]
+            k = d / math.sqrt(d.dot(d))
+            dT = T[t] - T[i]
+            Q[i] += rho[i] * sigma ** 2 * G * (-0.5 * T[i] * k.dot(v[:, t] - v[:, i]) + math.sqrt(T[i] / math.pi) * dT)
+            B[:, i] += -2 * T[i] * rho[i] * sigma ** 2 * k * G * dT
+            FT[:, i] += -0.5 * sigma ** 2 * k * G * dT
+    assert np.abs(Q_o - Q).max() < 1e-13 * np.abs(Q).max()
+    assert np.abs(B_o.reshape(3, N) - B).max() < 1e-13 * np.abs(B).max()
+    assert np.abs(FT_o.reshape(3, N) - FT).max() < 1e-13 * np.abs(FT).max()
