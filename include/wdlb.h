@@ -170,6 +170,27 @@ wdlb_status wdlb_read_profiles(wdlb_ctx *ctx, double *h_n_z, double *h_ux_z);
  * may be NULL. */
 wdlb_status wdlb_read_flux(wdlb_ctx *ctx, double *j_pore, double *u_pore, double *mass);
 
+/* Thermal fields of Sec. 3 at given fields (k_B = m = 1), with the
+ * context's sigma and shell (the contact value g_CS at the Fischer-Methfessel
+ * weighted density of the given n at each pair midpoint, as in the step):
+ *   h_Q[N]   energy source Q of eq. campob1,
+ *   h_B[3N]  heat-flux correction B_i of eq. campos,
+ *   h_FT[3N] thermal-gradient force F^T_i of eq. thermalforce,
+ * from h_n[N] density (>= 0), h_u[3N] velocity and h_T[N] temperature
+ * (> 0), all FP64 host arrays in the node order above (vectors
+ * component-major).  The isothermal step does not use these fields; this
+ * call evaluates them on request.  The fields are computed in the storage
+ * arithmetic (FP64 or FP32), the inputs rounded to it first; the outputs may
+ * be NULL.  The context's state is left as it was (the call may come before
+ * init or between steps; it reuses per-step arrays that the next step
+ * rewrites).  Errors: WDLB_E_INVAL for a null input, a negative or
+ * non-finite density, a non-positive temperature or a non-finite velocity;
+ * WDLB_E_UNSTABLE when a midpoint packing fraction of n reaches 1 (the
+ * fields are then not written).  The nonlocal and smdb switches of the step
+ * do not apply.  Synchronises. */
+wdlb_status wdlb_thermal_fields(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
+                                double *h_B, double *h_FT);
+
 /* Current post-stream populations f_a (19N, FP64, order above). */
 wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);
 
@@ -192,8 +213,8 @@ wdlb_status wdlb_get_step(const wdlb_ctx *ctx, int64_t *step);
  * id k (0 .. WDLB_NKERNELS-1), the summed device time in milliseconds and
  * the number of launches timed.  wdlb_kernel_name(k) names the kernel (""
  * for an unknown id): 0 moments, 1 density, 2 meanfield, 3 shell,
- * 4 collide. */
-#define WDLB_NKERNELS 5
+ * 4 collide (the step's), 5 thermal (of wdlb_thermal_fields). */
+#define WDLB_NKERNELS 6
 wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t mask);
 wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 const char *wdlb_kernel_name(int32_t kernel);

@@ -14,6 +14,7 @@
 
 #include "../../include/wdlb.h"
 #include "kernels.hpp"
+#include "thermal.hpp"
 
 using namespace wdlb;
 
@@ -421,8 +422,9 @@ wdlb_status tables(wdlb_ctx *c)
 
 inline dim3 grid1(long long N, int bs) { return dim3((unsigned)((N + bs - 1) / bs)); }
 
-enum { K_MOMENTS = 0, K_DENSITY, K_MEANFIELD, K_SHELL, K_COLLIDE };
-const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide"};
+enum { K_MOMENTS = 0, K_DENSITY, K_MEANFIELD, K_SHELL, K_COLLIDE, K_THERMAL };
+const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide",
+                                           "k_thermal"};
 
 // Timing events are created without the system-scope fence: a default event
 // writes back and invalidates the caches when it is recorded, which slows
@@ -761,6 +763,61 @@ size_t state_bytes(const wdlb_ctx *c)
     return sizeof(StateHeader) + 4 * c->rsize * N + (size_t)c->hplanes * c->hsize * N;
 }
 
+// Thermal fields at given n, u, T (wdlb_thermal_fields).  The inputs go to
+// per-step arrays that the next step rewrites before it reads them: n to
+// jx, T to jy, u to u_rd; then n is padded into the density array, the
+// contact values are formed by the step's density kernel, (n, u) is padded
+// into the (rho, u1) array and T over the padded density.  Q goes to rho_rd,
+// B to F and F^T to the first three planes of A.  The state is untouched.
+template <typename R>
+wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
+                                  double *h_B, double *h_FT)
+{
+    const Geom g = c->g;
+    const Pad pd = c->pad;
+    const size_t N = (size_t)g.N;
+    {
+        std::vector<R> v(N);
+        for (size_t i = 0; i < N; ++i) v[i] = (R)h_n[i];
+        HIPCHK(c, hipMemcpyAsync(c->jx, v.data(), N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < N; ++i) v[i] = (R)h_T[i];
+        HIPCHK(c, hipMemcpyAsync(c->jy, v.data(), N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<R> w(3 * N);
+        for (size_t i = 0; i < 3 * N; ++i) w[i] = (R)h_u[i];
+        HIPCHK(c, hipMemcpyAsync(c->u_rd, w.data(), 3 * N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    const dim3 grid = grid1(g.N, 256);
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    const int prof = c->prof;
+    c->prof = prof & (1 << K_THERMAL);  // only k_thermal is timed here
+    wdlb_status st = launch_density<R>(c);
+    c->prof = prof;
+    if (st != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_pad_ru<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (const R *)c->u_rd,
+                       (V4<R> *)c->ru1_p);
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jy, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8;
+    const double s = c->prm.sigma;
+    st = launch(c, K_THERMAL, [&] {
+        hipLaunchKernelGGL((k_thermal<R>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, pd,
+                           (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
+                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, (R *)c->rho_rd, (R *)c->F,
+                           (R *)c->A);
+    });
+    if (st != WDLB_OK) return st;
+    HIPCHK(c, hipGetLastError());
+    if ((st = check_flag(c)) != WDLB_OK) return st;
+    if ((st = copy_out_r(c, c->rho_rd, N, h_Q)) != WDLB_OK) return st;
+    if ((st = copy_out_r(c, c->F, 3 * N, h_B)) != WDLB_OK) return st;
+    return copy_out_r(c, c->A, 3 * N, h_FT);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1069,6 +1126,23 @@ wdlb_status wdlb_read_fields_ex(wdlb_ctx *c, double *h_n, double *h_u, double *h
 wdlb_status wdlb_read_fields(wdlb_ctx *c, double *h_n, double *h_u)
 {
     return wdlb_read_fields_ex(c, h_n, h_u, nullptr, nullptr);
+}
+
+wdlb_status wdlb_thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
+                                double *h_B, double *h_FT)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (!h_n || !h_u || !h_T) return fail(c, WDLB_E_INVAL, "null field");
+    if (c->g.zp != nullptr) return fail(c, WDLB_E_STATE, "thermal fields of a stacked lattice");
+    const size_t N = (size_t)c->g.N;
+    for (size_t i = 0; i < N; ++i) {
+        if (!(std::isfinite(h_n[i]) && h_n[i] >= 0.0)) return fail(c, WDLB_E_INVAL, "density negative or not finite");
+        if (!(std::isfinite(h_T[i]) && h_T[i] > 0.0)) return fail(c, WDLB_E_INVAL, "temperature not positive");
+    }
+    for (size_t i = 0; i < 3 * N; ++i)
+        if (!std::isfinite(h_u[i])) return fail(c, WDLB_E_INVAL, "velocity not finite");
+    if (c->store == WDLB_FP64) return thermal_fields<double>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
+    return thermal_fields<float>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
 }
 
 static wdlb_status planes(wdlb_ctx *c, std::vector<double> &out)

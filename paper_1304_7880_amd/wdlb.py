@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libwdlb.so")
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSTABLE, E_STATE, E_NOT_CONVERGED = range(7)
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSTABLE", 5: "E_STATE", 6: "E_NOT_CONVERGED"}
 FP64, FP32, BF16_NEQ, FP32_LOCAL64, BF16_NEQ_LOCAL64 = 0, 1, 2, 3, 4
-NKERNELS = 5
+NKERNELS = 6
 NTILES = 7
 PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16_NEQ, "fp32_local64": FP32_LOCAL64,
              "bf16_local64": BF16_NEQ_LOCAL64}
@@ -30,7 +30,7 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 
 SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_create_static", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
-           "wdlb_read_flux", "wdlb_read_populations", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
+           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
            "wdlb_get_tile", "wdlb_set_graphs", "wdlb_last_error", "wdlb_destroy",
            "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     L.wdlb_read_profiles.argtypes = [vp, dp, dp]
     L.wdlb_read_flux.argtypes = [vp, dp, dp, dp]
     L.wdlb_read_populations.argtypes = [vp, dp]
+    L.wdlb_thermal_fields.argtypes = [vp, dp, dp, dp, dp, dp, dp]
     L.wdlb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.wdlb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.wdlb_load_state.argtypes = [vp, vp, C.c_size_t]
@@ -249,6 +250,21 @@ class Context:
         j, u, m = C.c_double(), C.c_double(), C.c_double()
         self._chk(self._L.wdlb_read_flux(self.h, C.byref(j), C.byref(u), C.byref(m)), "read_flux")
         return j.value, u.value, m.value
+
+    def thermal_fields(self, n, u, T):
+        """(Q[N], B[3N], F^T[3N]) of Sec. 3 (eqs. campob1, campos,
+        thermalforce) at the given density n[N], velocity u[3N] and
+        temperature T[N]; the state is left as it was."""
+        N = self.N
+        n = np.ascontiguousarray(n, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        if n.size != N or u.size != 3 * N or T.size != N:
+            raise ValueError("field sizes do not match the lattice")
+        Q, B, FT = np.zeros(N), np.zeros(3 * N), np.zeros(3 * N)
+        self._chk(self._L.wdlb_thermal_fields(self.h, _ptr(n), _ptr(u), _ptr(T), _ptr(Q), _ptr(B), _ptr(FT)),
+                  "thermal_fields")
+        return Q, B, FT
 
     def read_populations(self):
         f = np.zeros(19 * self.N)

@@ -94,6 +94,12 @@ def random_fields(nx, ny, nz, n0, rel=0.05, uamp=0.01, seed=0):
     return n, u
 
 
+def random_temperature(nx, ny, nz, T0=1.0 / 3.0, rel=0.1, seed=0):
+    """Random temperature field T = T0 (1 + rel xi), xi uniform in [-1, 1] (N)."""
+    rng = np.random.default_rng(seed)
+    return T0 * (1.0 + rel * rng.uniform(-1.0, 1.0, nx * ny * nz))
+
+
 # --------------------------------------------------------------------------
 # Serving workload: slit-pore solves arriving as a Poisson stream.
 # --------------------------------------------------------------------------

@@ -154,7 +154,16 @@ def test_slab64_same_input_3d_oracle(prec, tol, ckpts):
     (tests/golden/make_slab64_3d_ref.py): at each stored step the plane
     means n(z), u_x(z), the pore flux, the mean velocity and the mass, and
     density and velocity at a few single nodes (walls, mid-pore, ragged tile
-    positions), where the noise-driven flow is still three-dimensional."""
+    positions), where the noise-driven flow is still three-dimensional.
+
+    Single-node velocities in FP32 storage carry the rounding of the stored
+    density of the neighbours that the pull reads (relative 6e-8 of n, with n
+    varying by a factor of ~2 across the wall layers): an absolute error of
+    order 1e-8 to 1e-7 in u at every step, which does not grow and which the
+    plane means average out (measured: at most 2.1e-7 over all nodes up to
+    step 2000, in both FP32 modes).  The node-velocity bar is therefore
+    absolute there, 1e-6 (about 17 FP32 ulps of the lattice speed); in FP64
+    it is relative, 10 x the bar of the means."""
     from paper_1304_7880_amd import wdlb
     from paper_1304_7880_amd.workloads import SLAB_64
     ref = _golden("slab64_3d_oracle.json")
@@ -184,11 +193,15 @@ def test_slab64_same_input_3d_oracle(prec, tol, ckpts):
         pr_g = np.array([[rho_g[i], u_g[i], u_g[w.N + i], u_g[2 * w.N + i]]
                          for i in ((z * w.ny + y) * w.nx + x for x, y, z in ref["probes"])])
         e_pr = float(np.abs(pr_g[:, 0] - pr_o[:, 0]).max() / np.abs(pr_o[:, 0]).max())
-        e_pu = float(np.abs(pr_g[:, 1:] - pr_o[:, 1:]).max() / np.abs(pr_o[:, 1:]).max())
+        d_pu = float(np.abs(pr_g[:, 1:] - pr_o[:, 1:]).max())
+        e_pu = d_pu / float(np.abs(pr_o[:, 1:]).max())
         _say(f"  step {t}: u_x(z) {e_u:.2e} n(z) {e_n:.2e} J {e_J:.2e} u_pore {e_U:.2e} mass {e_M:.2e} "
-             f"node rho {e_pr:.2e} node u {e_pu:.2e}")
+             f"node rho {e_pr:.2e} node u {e_pu:.2e} (abs {d_pu:.2e})")
         assert e_u < tol and e_J < tol and e_U < tol, t
         assert e_n < tol and e_pr < tol, t
         assert e_M < (1e-13 if prec == "fp64" else 1e-6), t
-        assert e_pu < 10 * tol, t
+        if prec == "fp64":
+            assert e_pu < 10 * tol, t
+        else:
+            assert d_pu < 1e-6, t
     ctx.destroy()
