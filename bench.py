@@ -301,6 +301,48 @@ def transport_bench(parts=("bulk", "sound", "slit")):
 
 SURVEY_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
 
+# Thermal fields (Q, B_i, F^T of Sec. 3) per shell offset: dT, G = gamma rho,
+# D = G dT, k_i D (3 FMA), sum D, du (3), V = G du (3), k.V (3 FMA):
+# 16 operations, 22 flops (an FMA counted as 2).
+THERMAL_OPS_PER_OFFSET = 16.0
+THERMAL_FLOPS_PER_OFFSET = 22.0
+
+
+def thermal_bench(w, prec, reps=5):
+    """The thermal fields at seeded random n, u, T on workload w: k_thermal's
+    mean duration by HIP events over reps calls, its rate against the FP32
+    vector peak, and the host-inclusive time of one call (the fields cross
+    PCIe both ways)."""
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import random_fields, random_temperature
+    n, u = random_fields(w.nx, w.ny, w.nz, w.n0, 0.05, 0.01, seed=1)
+    T = random_temperature(w.nx, w.ny, w.nz, 1.0 / 3.0, 0.1, seed=2)
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, prec, w.sigma, w.eta, w.tau, w.g)
+    ctx.thermal_fields(n, u, T)
+    ctx.profile(True, kernels=["k_thermal"])
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.thermal_fields(n, u, T)
+    call_s = (time.perf_counter() - t0) / reps
+    ms, cnt = ctx.profile_read()["k_thermal"]
+    ctx.profile(False)
+    tile, spec = ctx.get_tile()
+    ctx.destroy()
+    k_s = ms / cnt * 1e-3
+    nS = shell_size(w.sigma)
+    ops = THERMAL_OPS_PER_OFFSET * nS * w.N
+    flops = THERMAL_FLOPS_PER_OFFSET * nS * w.N
+    return {"workload": w.name, "precision": PRECISION_LABEL[prec],
+            "kernel": "k_thermal_s" if (spec and prec != "fp64") else "k_thermal_r",
+            "avg_kernel_ms": round(ms / cnt, 5), "launches": cnt,
+            "call_ms_host_inclusive": round(call_s * 1e3, 2),
+            "roofline": {"bound": "alu", "achieved": round(ops / k_s / 1e12, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ops / k_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                         "count": f"{THERMAL_OPS_PER_OFFSET:g} operations per shell offset x {nS} offsets x "
+                                  f"{w.N} nodes",
+                         "achieved_22flop": round(flops / k_s / 1e12, 3),
+                         "frac_22flop": round(flops / k_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}}
+
 
 def timed_run(w, precision, steps, warmup, stream, init_fields=None):
     """Warm up, then time exactly `steps` steps of workload w between
@@ -343,7 +385,7 @@ def timed_run(w, precision, steps, warmup, stream, init_fields=None):
     torch.cuda.empty_cache()
     return {"dev_ms": dev_ms, "wall_s": wall, "ms_per_step": dev_ms / steps,
             "mlups": w.N * steps / (dev_ms * 1e-3) / 1e6, "shell_name": shell_name,
-            "shell_avg_ms": k_ms / k_n, "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kstats.items()},
+            "shell_avg_ms": k_ms / k_n, "kernels_ms_per_step": {k: v[0] / v[1] for k, v in kstats.items() if v[1]},
             "pore_flux": J}
 
 
@@ -379,6 +421,8 @@ def main():
                     help="slab512: the 512x512x256 slab at sigma = 10 (default); slab64: the 64x64x64 slit")
     ap.add_argument("--precision", choices=tuple(PRECISION_LABEL), default="fp32_local64",
                     help="storage and local arithmetic of the timed lattice")
+    ap.add_argument("--thermal", action="store_true",
+                    help="time only the thermal-field kernel (Q, B_i, F^T) on the workload; one JSON line")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
                     help="run the transport experiments instead (comma list of bulk, sound, slit; default all); "
                          "one JSON line")
@@ -402,6 +446,9 @@ def main():
         if not parts or set(parts) - {"bulk", "sound", "slit"}:
             sys.exit("--transport takes a comma list of bulk, sound, slit")
         print(json.dumps(transport_bench(parts)), flush=True)
+        return
+    if args.thermal:
+        print(json.dumps(thermal_bench(w, args.precision)), flush=True)
         return
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
@@ -472,6 +519,8 @@ def main():
             out["slab64"] = {"workload": SLAB_64.name, "mlups": round(m["mlups"], 2),
                              "ms_per_step": round(m["ms_per_step"], 5), "steps": 200,
                              "kernels_ms_per_step": {k: round(v, 5) for k, v in m["kernels_ms_per_step"].items()}}
+        print(f"bench: thermal fields on {w.name}", file=sys.stderr, flush=True)
+        out["thermal_fields"] = thermal_bench(w, args.precision)
     if args.serving:
         out["serving"] = serving_bench(args.serving, args.serving_planes, args.serving_max_steps,
                                        plain=not args.serving_no_plain)

@@ -240,7 +240,10 @@ const char *wdlb_kernel_name(int32_t kernel);
  * table-driven kernels and fails with WDLB_E_INVAL, leaving the previous
  * choice, when it does not fit.  wdlb_set_params re-applies the request for
  * the new sigma.  wdlb_get_tile returns the variant in use and (if
- * specialised is not NULL) 1 when the compiled-shell kernels run, else 0. */
+ * specialised is not NULL) 1 when the compiled-shell kernels run, else 0.
+ * wdlb_thermal_fields follows the same request: its compiled-shell kernel
+ * (FP32, sigma = 3, 4, 6, 8 or 10) runs only under the automatic choice,
+ * its table-driven kernels (same result, bit for bit) under a forced one. */
 #define WDLB_NTILES 7
 wdlb_status wdlb_set_tile(wdlb_ctx *ctx, int32_t variant);
 wdlb_status wdlb_get_tile(wdlb_ctx *ctx, int32_t *variant, int32_t *specialised);

@@ -39,14 +39,69 @@ __global__ __launch_bounds__(256) void k_pad_ru(Geom g, Pad p, const R *__restri
     for_images(g, p, x, y, z, [&](int k) { dst[k] = v; });
 }
 
-// One lane per node on 32 x 8 tiles of a plane; the shell from the quad
-// table (mirror groups (+-a, +-b, c)), the images' rho, u, T and contact
-// values read through the caches.  Per group: the four image terms
-// D_m = G_m dT_m and V_m = G_m dv_m (products unfused, as in the step's
-// shell sums), their Hadamard transform over the mirror signs, and one FMA
-// per weight.  A state that does not depend on x (or y) gives exactly zero
-// x (y) components.  The contact values of the density kernel carry the
-// shell weight w_S; s2 = sigma^2.
+// One mirror group of the thermal sums from its four images: s (rho, u), tm
+// (T) and gm (contact value with w_S).  D_m = G_m dT_m and V_m = G_m dv_m,
+// products unfused as in the step's shell sums, then the Hadamard transform
+// over the mirror signs and one FMA per weight.  w is the group's plain
+// weight: 1, or 1/2 (1/4) when a (and b) is zero and its images repeat;
+// px, py, pz carry it times k.
+template <typename R>
+__device__ __forceinline__ void th_quad(const Quad<R> &Qd, const R (&gm)[4], const V4<R> (&sm)[4], const R (&tm)[4],
+                                        const V4<R> &c0, R T0, R &ax, R &ay, R &az, R &aT, R &aV)
+{
+    const R w = R(Qd.a > 0 ? 1.0 : 0.5) * R(Qd.b > 0 ? 1.0 : 0.5);
+    R hx, hy, h0, vx, vy, vz;
+    {
+#pragma clang fp contract(off)
+        R D[4], Vx[4], Vy[4], Vz[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const R G = gm[m] * sm[m].x;
+            D[m] = G * (tm[m] - T0);
+            Vx[m] = G * (sm[m].y - c0.y);
+            Vy[m] = G * (sm[m].z - c0.z);
+            Vz[m] = G * (sm[m].w - c0.w);
+        }
+        const R P1 = D[0] + D[1], M1 = D[0] - D[1], P2 = D[2] + D[3], M2 = D[2] - D[3];
+        hx = M1 + M2;
+        hy = P1 - P2;
+        h0 = P1 + P2;
+        vx = (Vx[0] - Vx[1]) + (Vx[2] - Vx[3]);
+        vy = (Vy[0] + Vy[1]) - (Vy[2] + Vy[3]);
+        vz = (Vz[0] + Vz[1]) + (Vz[2] + Vz[3]);
+    }
+    ax += Qd.px * hx;
+    ay += Qd.py * hy;
+    az += Qd.pz * h0;
+    aT += w * h0;
+    aV += Qd.px * vx;
+    aV += Qd.py * vy;
+    aV += Qd.pz * vz;
+}
+
+// Q, B and F^T of the node from the five sums
+template <typename R>
+__device__ __forceinline__ void th_finish(const Geom &g, int x, int y, int z, R n0, R T0, R s2, R ax, R ay, R az,
+                                          R aT, R aV, R *__restrict__ Qo, R *__restrict__ Bo, R *__restrict__ FTo)
+{
+    const long long N = g.N;
+    const int i = (z * g.ny + y) * g.nx + x;
+    const R kq = n0 * s2, kb = R(-2) * T0 * n0 * s2, kf = R(-0.5) * s2;
+    Qo[i] = kq * (R(-0.5) * T0 * aV + sqrt(T0 / R(M_PI)) * aT);
+    Bo[i] = kb * ax;
+    Bo[N + i] = kb * ay;
+    Bo[2 * N + i] = kb * az;
+    FTo[i] = kf * ax;
+    FTo[N + i] = kf * ay;
+    FTo[2 * N + i] = kf * az;
+}
+
+// k_thermal: one lane per node on 32 x 8 tiles of a plane; the shell from
+// the quad table (mirror groups (+-a, +-b, c), in the table's order), the
+// images' rho, u, T and contact values read through the caches.  A state
+// that does not depend on x (or y) gives exactly zero x (y) components.  The
+// contact values of the density kernel carry the shell weight w_S;
+// s2 = sigma^2.  Used where the LDS rings of k_thermal_r do not fit.
 template <typename R>
 __global__ __launch_bounds__(256) void k_thermal(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
                                                  const R *__restrict__ T_p, const R *__restrict__ gam_p,
@@ -66,48 +121,245 @@ __global__ __launch_bounds__(256) void k_thermal(Geom g, Pad p, const V4<R> *__r
         int so[4], mo[4];
         quad_offsets(Qd.a, Qd.b, Qd.c, p.PX, p.PXY, so, mo);
         const R *gb = gam_p + (long long)Qd.hidx * p.NP + gbase;
-        // the plain weight of the group: 1, 1/2 or 1/4 for a or b zero (its
-        // images repeat); px, py, pz carry it times k
-        const R w = R(Qd.a > 0 ? 1.0 : 0.5) * R(Qd.b > 0 ? 1.0 : 0.5);
-        R hx, hy, h0, vx, vy, vz;
-        {
-#pragma clang fp contract(off)
-            R D[4], Vx[4], Vy[4], Vz[4];
+        R gm[4], tm[4];
+        V4<R> sm[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const V4<R> s = ru_p[gbase + so[m]];
-                const R G = gb[mo[m]] * s.x;
-                D[m] = G * (T_p[gbase + so[m]] - T0);
-                Vx[m] = G * (s.y - c0.y);
-                Vy[m] = G * (s.z - c0.z);
-                Vz[m] = G * (s.w - c0.w);
-            }
-            const R P1 = D[0] + D[1], M1 = D[0] - D[1], P2 = D[2] + D[3], M2 = D[2] - D[3];
-            hx = M1 + M2;
-            hy = P1 - P2;
-            h0 = P1 + P2;
-            vx = (Vx[0] - Vx[1]) + (Vx[2] - Vx[3]);
-            vy = (Vy[0] + Vy[1]) - (Vy[2] + Vy[3]);
-            vz = (Vz[0] + Vz[1]) + (Vz[2] + Vz[3]);
+        for (int m = 0; m < 4; ++m) {
+            gm[m] = gb[mo[m]];
+            sm[m] = ru_p[gbase + so[m]];
+            tm[m] = T_p[gbase + so[m]];
         }
-        ax += Qd.px * hx;
-        ay += Qd.py * hy;
-        az += Qd.pz * h0;
-        aT += w * h0;
-        aV += Qd.px * vx;
-        aV += Qd.py * vy;
-        aV += Qd.pz * vz;
+        th_quad<R>(Qd, gm, sm, tm, c0, T0, ax, ay, az, aT, aV);
     }
-    const long long N = g.N;
-    const int i = (z * g.ny + y) * g.nx + x;
-    const R n0 = c0.x, kq = n0 * s2, kb = R(-2) * T0 * n0 * s2, kf = R(-0.5) * s2;
-    Qo[i] = kq * (R(-0.5) * T0 * aV + sqrt(T0 / R(M_PI)) * aT);
-    Bo[i] = kb * ax;
-    Bo[N + i] = kb * ay;
-    Bo[2 * N + i] = kb * az;
-    FTo[i] = kf * ax;
-    FTo[N + i] = kf * ay;
-    FTo[2 * N + i] = kf * az;
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+}
+
+// k_thermal_r: the same sums on TX x TY x TZ tiles with (rho, u) and T
+// staged in two LDS rings of planes that advance along e_z (the plane ring
+// of the step's shell kernels, one for V4 (rho, u) and one for T; see
+// ShellRings), the contact values read through the caches.  The groups are
+// visited in the same order as by k_thermal, with the same arithmetic, so
+// the two kernels give the same bits.
+template <typename R, int TX, int TY, int TZ, int NR>
+__global__ __launch_bounds__(TX *TY *TZ) void k_thermal_r(Geom g, Pad p, int Rr, const V4<R> *__restrict__ ru_p,
+                                                          const R *__restrict__ T_p, const R *__restrict__ gam_p,
+                                                          const Quad<R> *__restrict__ quads,
+                                                          const int *__restrict__ qstart, R s2, int tiles_x,
+                                                          int tiles_y, int tiles_z, R *__restrict__ Qo,
+                                                          R *__restrict__ Bo, R *__restrict__ FTo)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, V4<R>, TX, TY, TZ, NR, 0> rg;   // (rho, u) ring; fill ends with a barrier
+    rg.init(lds_raw, p, Rr, tc, ru_p, gam_p);
+    constexpr int NT = TX * TY * TZ, NS = TZ + 1;
+    PlaneRing<R, R, NT, NR> tr;                    // T ring after the (rho, u) ring
+    tr.setup(p, Rr, TX, TY, tc.x0, tc.y0);
+    R *twin = reinterpret_cast<R *>(lds_raw + (size_t)NS * rg.pr.LP * sizeof(V4<R>));
+    {
+        R tst[TZ][1][NR];
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) tr.fetch_to(tst[k], T_p, p, tc.z0 - Rr + k);
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) tr.store_all(tst[k], twin, k);
+    }
+    __syncthreads();
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const V4<R> c0 = ru_p[gbase];
+    const R T0 = T_p[gbase];
+    const int LX = rg.pr.LX;
+    constexpr int QB = 8;
+    R ax = 0, ay = 0, az = 0, aT = 0, aV = 0;
+    for (int c = -Rr; c <= Rr; ++c) {
+        rg.template begin<0>(c, p, ru_p, gam_p);
+        if (c < Rr) tr.template fetch<0, true>(T_p, p, tc.z0 + c + TZ);
+        const V4<R> *pl = rg.plane(c);
+        const R *tl = twin + ((tc.lz + c + Rr) % NS) * tr.LP + rg.lbase;
+        const int qb = qstart[c + Rr], qe = qstart[c + Rr + 1];
+        // contact values of QB groups at a time, all loads issued before the
+        // first is used (one cache latency per batch rather than per group)
+        for (int q0 = qb; q0 < qe; q0 += QB) {
+            R gb[QB][4];
+#pragma unroll
+            for (int k = 0; k < QB; ++k)
+                if (q0 + k < qe) {
+                    const Quad<R> Qd = quads[q0 + k];
+                    gamma_quad<R, false>(nullptr, 0, 0, gam_p, p, gbase, Qd.a, Qd.b, Qd.c, Qd.hidx, gb[k]);
+                }
+#pragma unroll
+            for (int k = 0; k < QB; ++k)
+                if (q0 + k < qe) {
+                    const Quad<R> Qd = quads[q0 + k];
+                    const int a = Qd.a, b = Qd.b;
+                    R tm[4];
+                    V4<R> sm[4];
+                    sm[0] = pl[a + b * LX];
+                    sm[1] = pl[-a + b * LX];
+                    sm[2] = pl[a - b * LX];
+                    sm[3] = pl[-a - b * LX];
+                    tm[0] = tl[a + b * LX];
+                    tm[1] = tl[-a + b * LX];
+                    tm[2] = tl[a - b * LX];
+                    tm[3] = tl[-a - b * LX];
+                    th_quad<R>(Qd, gb[k], sm, tm, c0, T0, ax, ay, az, aT, aV);
+                }
+        }
+        if (c < Rr) tr.template store<0>(twin, (c + TZ + Rr) % NS);
+        rg.template end<0>(c);   // stores the next (rho, u) plane, then the barrier
+    }
+    if (!valid) return;
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+}
+
+// k_thermal_s: the same sums compiled for the shell of 2 sigma = S2 (FP32):
+// the e_z steps and the groups unrolled, every LDS offset an immediate,
+// every weight a literal; the contact values by buffer loads whose image
+// offset is a scalar (see gamma_img).  Groups with a or b zero sum their
+// distinct images once with doubled (quadrupled) weights, which is exact, so
+// the result is bit-identical to k_thermal_r and k_thermal.
+template <typename R, int S2, int TX, int TY, int TZ, int NR>
+__global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
+                                                          const R *__restrict__ T_p, const R *__restrict__ gam_p,
+                                                          R s2, int tiles_x, int tiles_y, int tiles_z,
+                                                          R *__restrict__ Qo, R *__restrict__ Bo, R *__restrict__ FTo)
+{
+    static_assert(sizeof(R) == 4, "compiled thermal sums read the contact values by FP32 buffer loads");
+    using SH = Shell<S2>;
+    constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, NT = TX * TY * TZ, NS = TZ + 1;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    ShellRings<R, V4<R>, TX, TY, TZ, NR, 0> rg;
+    rg.init(lds_raw, p, RC, tc, ru_p, gam_p);
+    PlaneRing<R, R, NT, NR> tr;
+    tr.setup(p, RC, TX, TY, tc.x0, tc.y0);
+    R *twin = reinterpret_cast<R *>(lds_raw + (size_t)NS * rg.pr.LP * sizeof(V4<R>));
+    {
+        R tst[TZ][1][NR];
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) tr.fetch_to(tst[k], T_p, p, tc.z0 - RC + k);
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) tr.store_all(tst[k], twin, k);
+    }
+    __syncthreads();
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const unsigned gvo = (unsigned)gbase * (unsigned)sizeof(R);
+    const V4<R> c0 = ru_p[gbase];
+    const R T0 = T_p[gbase];
+    R ax = 0, ay = 0, az = 0, aT = 0, aV = 0;
+    static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
+        constexpr int c = decltype(ci)::value;
+        rg.template begin<0>(c, p, ru_p, gam_p);
+        if constexpr (c < RC) tr.template fetch<0, true>(T_p, p, tc.z0 + c + TZ);
+        const V4<R> *pc = rg.plane(c) - (RC + RC * LX);
+        const R *tcp = twin + ((tc.lz + c + RC) % NS) * tr.LP + rg.lbase - (RC + RC * LX);
+        __amdgpu_buffer_rsrc_t gr[4];
+        gamma_rsrc<R>(gam_p, p, c, O, gr);
+        static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
+            constexpr CQuad Q = SH::T.q[decltype(qi)::value];
+            constexpr int a = Q.a, b = Q.b;
+#define WDLB_TGAM(SA, SB) gamma_img<R, false, O, 1, 1, a, b, Q.h, SA, SB>(nullptr, gr, p.PX, gvo)
+            if constexpr (a == 0 && b == 0) {
+                R D, Vz;
+                {
+#pragma clang fp contract(off)
+                    const V4<R> sv = pc[RC + RC * LX];
+                    const R G = WDLB_TGAM(1, 1) * sv.x;
+                    D = G * (tcp[RC + RC * LX] - T0);
+                    Vz = G * (sv.w - c0.w);
+                }
+                az += R(4 * Q.pz) * D;
+                aT += D;
+                aV += R(4 * Q.pz) * Vz;
+            } else if constexpr (a == 0) {  // images (0, b), (0, -b)
+                R dp, dm, vy, vz;
+                {
+#pragma clang fp contract(off)
+                    const V4<R> s0 = pc[RC + (RC + b) * LX], s2_ = pc[RC + (RC - b) * LX];
+                    const R G0 = WDLB_TGAM(1, 1) * s0.x, G2 = WDLB_TGAM(1, -1) * s2_.x;
+                    const R D0 = G0 * (tcp[RC + (RC + b) * LX] - T0), D2 = G2 * (tcp[RC + (RC - b) * LX] - T0);
+                    dp = D0 + D2;
+                    dm = D0 - D2;
+                    vy = G0 * (s0.z - c0.z) - G2 * (s2_.z - c0.z);
+                    vz = G0 * (s0.w - c0.w) + G2 * (s2_.w - c0.w);
+                }
+                ay += R(2 * Q.py) * dm;
+                az += R(2 * Q.pz) * dp;
+                aT += dp;
+                aV += R(2 * Q.py) * vy;
+                aV += R(2 * Q.pz) * vz;
+            } else if constexpr (b == 0) {  // images (a, 0), (-a, 0)
+                R dp, dm, vx, vz;
+                {
+#pragma clang fp contract(off)
+                    const V4<R> s0 = pc[(RC + a) + RC * LX], s1 = pc[(RC - a) + RC * LX];
+                    const R G0 = WDLB_TGAM(1, 1) * s0.x, G1 = WDLB_TGAM(-1, 1) * s1.x;
+                    const R D0 = G0 * (tcp[(RC + a) + RC * LX] - T0), D1 = G1 * (tcp[(RC - a) + RC * LX] - T0);
+                    dp = D0 + D1;
+                    dm = D0 - D1;
+                    vx = G0 * (s0.y - c0.y) - G1 * (s1.y - c0.y);
+                    vz = G0 * (s0.w - c0.w) + G1 * (s1.w - c0.w);
+                }
+                ax += R(2 * Q.px) * dm;
+                az += R(2 * Q.pz) * dp;
+                aT += dp;
+                aV += R(2 * Q.px) * vx;
+                aV += R(2 * Q.pz) * vz;
+            } else {
+                const R gm[4] = {WDLB_TGAM(1, 1), WDLB_TGAM(-1, 1), WDLB_TGAM(1, -1), WDLB_TGAM(-1, -1)};
+                const V4<R> sm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                                     pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+                const R tm[4] = {tcp[(RC + a) + (RC + b) * LX], tcp[(RC - a) + (RC + b) * LX],
+                                 tcp[(RC + a) + (RC - b) * LX], tcp[(RC - a) + (RC - b) * LX]};
+                R hx, hy, h0, vx, vy, vz;
+                {
+#pragma clang fp contract(off)
+                    R D[4], Vx[4], Vy[4], Vz[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const R G = gm[m] * sm[m].x;
+                        D[m] = G * (tm[m] - T0);
+                        Vx[m] = G * (sm[m].y - c0.y);
+                        Vy[m] = G * (sm[m].z - c0.z);
+                        Vz[m] = G * (sm[m].w - c0.w);
+                    }
+                    const R P1 = D[0] + D[1], M1 = D[0] - D[1], P2 = D[2] + D[3], M2 = D[2] - D[3];
+                    hx = M1 + M2;
+                    hy = P1 - P2;
+                    h0 = P1 + P2;
+                    vx = (Vx[0] - Vx[1]) + (Vx[2] - Vx[3]);
+                    vy = (Vy[0] + Vy[1]) - (Vy[2] + Vy[3]);
+                    vz = (Vz[0] + Vz[1]) + (Vz[2] + Vz[3]);
+                }
+                ax += R(Q.px) * hx;
+                ay += R(Q.py) * hy;
+                az += R(Q.pz) * h0;
+                aT += h0;
+                aV += R(Q.px) * vx;
+                aV += R(Q.py) * vy;
+                aV += R(Q.pz) * vz;
+            }
+#undef WDLB_TGAM
+        });
+        pin(ax);
+        pin(ay);
+        pin(az);
+        pin(aT);
+        pin(aV);
+        if constexpr (c < RC) tr.template store<0>(twin, (c + TZ + RC) % NS);
+        rg.template end<0>(c);
+    });
+    if (!valid) return;
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+}
+
+// LDS bytes of k_thermal_r: the (rho, u) ring, then the T ring
+__host__ __device__ constexpr size_t thermal_lds_bytes(int TX, int TY, int TZ, int Rr, size_t rbytes)
+{
+    return (size_t)(TZ + 1) * (TX + 2 * Rr) * (TY + 2 * Rr) * 5 * rbytes;
 }
 
 }  // namespace wdlb

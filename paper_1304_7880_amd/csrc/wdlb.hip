@@ -763,6 +763,103 @@ size_t state_bytes(const wdlb_ctx *c)
     return sizeof(StateHeader) + 4 * c->rsize * N + (size_t)c->hplanes * c->hsize * N;
 }
 
+// The thermal-field kernels: compiled for the shell (FP32, compiled sigma),
+// else table-driven on LDS-ring tiles (32 x 8 x 2 in FP32, 32 x 8 x 1 in
+// FP64) where the two rings fit, else the cache kernel.
+template <typename R, int TZ, int NR>
+wdlb_status launch_thermal_r(wdlb_ctx *c)
+{
+    const Geom g = c->g;
+    const double s = c->prm.sigma;
+    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8, tz = (g.nz + TZ - 1) / TZ;
+    const size_t lds = thermal_lds_bytes(32, 8, TZ, c->reach, sizeof(R));
+    auto kern = k_thermal_r<R, 32, 8, TZ, NR>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return launch(c, K_THERMAL, [&] {
+        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(32 * 8 * TZ), lds, c->stream, g, c->pad,
+                           c->reach, (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
+                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(s * s), tx, ty, tz, (R *)c->rho_rd,
+                           (R *)c->F, (R *)c->A);
+    });
+}
+
+// compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
+// sigma = 10 their two rings (75 KB) leave room for two blocks per CU
+template <int S2>
+wdlb_status launch_thermal_s(wdlb_ctx *c)
+{
+    constexpr int TX = 32, TY = 16, TZ = 1, NT = TX * TY * TZ;
+    constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
+    static_assert(thermal_lds_bytes(TX, TY, TZ, RC, 4) <= LDS_MAX, "rings fit in LDS");
+    if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
+    const Geom g = c->g;
+    const double s = c->prm.sigma;
+    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
+    const size_t lds = thermal_lds_bytes(TX, TY, TZ, RC, 4);
+    auto kern = k_thermal_s<float, S2, TX, TY, TZ, NR>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return launch(c, K_THERMAL, [&] {
+        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
+                           (const V4<float> *)c->ru1_p, (const float *)c->rho_p, (const float *)c->gam_p,
+                           float(s * s), tx, ty, tz, (float *)c->rho_rd, (float *)c->F, (float *)c->A);
+    });
+}
+
+template <typename R>
+wdlb_status launch_thermal(wdlb_ctx *c)
+{
+    if constexpr (std::is_same<R, float>::value) {
+        // the buffer loads of the contact values take a lane offset below
+        // 2^31 bytes into one padded sub-lattice; a forced shell tile
+        // (wdlb_set_tile >= 0) selects the table-driven kernels here too
+        if (c->tile_req < 0 && 4.0 * (double)c->pad.NP < 2.0e9) {
+            switch (specialised_s2(c->prm.sigma)) {
+            case 6: return launch_thermal_s<6>(c);
+            case 8: return launch_thermal_s<8>(c);
+            case 12: return launch_thermal_s<12>(c);
+            case 16: return launch_thermal_s<16>(c);
+            case 20: return launch_thermal_s<20>(c);
+            default: break;
+            }
+        }
+    }
+    constexpr int TZ = std::is_same<R, float>::value ? 2 : 1;
+    const int Rr = c->reach, LP = (32 + 2 * Rr) * (8 + 2 * Rr), nr = (LP + 32 * 8 * TZ - 1) / (32 * 8 * TZ);
+    if (thermal_lds_bytes(32, 8, TZ, Rr, sizeof(R)) <= LDS_MAX) {
+        if constexpr (TZ == 2) {
+            switch (nr) {
+            case 1: return launch_thermal_r<R, TZ, 1>(c);
+            case 2: return launch_thermal_r<R, TZ, 2>(c);
+            case 3: return launch_thermal_r<R, TZ, 3>(c);
+            case 4: return launch_thermal_r<R, TZ, 4>(c);
+            case 5: return launch_thermal_r<R, TZ, 5>(c);
+            default: break;
+            }
+        } else {
+            switch (nr) {
+            case 1: return launch_thermal_r<R, TZ, 1>(c);
+            case 2: return launch_thermal_r<R, TZ, 2>(c);
+            case 3: return launch_thermal_r<R, TZ, 3>(c);
+            case 4: return launch_thermal_r<R, TZ, 4>(c);
+            case 5: return launch_thermal_r<R, TZ, 5>(c);
+            case 6: return launch_thermal_r<R, TZ, 6>(c);
+            case 7: return launch_thermal_r<R, TZ, 7>(c);
+            case 8: return launch_thermal_r<R, TZ, 8>(c);
+            default: break;
+            }
+        }
+    }
+    const Geom g = c->g;
+    const double s = c->prm.sigma;
+    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8;
+    return launch(c, K_THERMAL, [&] {
+        hipLaunchKernelGGL((k_thermal<R>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, c->pad,
+                           (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
+                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, (R *)c->rho_rd, (R *)c->F,
+                           (R *)c->A);
+    });
+}
+
 // Thermal fields at given n, u, T (wdlb_thermal_fields).  The inputs go to
 // per-step arrays that the next step rewrites before it reads them: n to
 // jx, T to jy, u to u_rd; then n is padded into the density array, the
@@ -802,14 +899,7 @@ wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, co
                        (V4<R> *)c->ru1_p);
     hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jy, (R *)c->rho_p);
     HIPCHK(c, hipGetLastError());
-    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8;
-    const double s = c->prm.sigma;
-    st = launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL((k_thermal<R>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, pd,
-                           (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, (R *)c->rho_rd, (R *)c->F,
-                           (R *)c->A);
-    });
+    st = launch_thermal<R>(c);
     if (st != WDLB_OK) return st;
     HIPCHK(c, hipGetLastError());
     if ((st = check_flag(c)) != WDLB_OK) return st;

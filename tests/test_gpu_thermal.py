@@ -43,6 +43,9 @@ CASES = [
     ("periodic 14x13x15 sigma=5.5 (non-integer sigma)", (14, 13, 15), False, 5.5, 0.3),
     ("walled 33x10x20 sigma=7 (table-driven density)", (33, 10, 20), True, 7.0, 0.25),
     ("walled 22x21x26 sigma=10", (22, 21, 26), True, 10.0, 0.3),
+    ("walled 27x26x30 sigma=12", (27, 26, 30), True, 12.0, 0.2),
+    # reach 16: the FP64 rings do not fit in LDS, the kernel reads through the caches
+    ("walled 20x18x36 sigma=16 (largest sigma)", (20, 18, 36), True, 16.0, 0.2),
 ]
 
 
@@ -183,3 +186,21 @@ def test_full_size_slab_z_profile_against_column():
     _say(f"  Q {eq:.2e}  B_z {eb:.2e}  F^T_z {ef:.2e}")
     assert not B[:2 * nz * m].any() and not FT[:2 * nz * m].any()
     assert max(eq, eb, ef) < 2e-5
+
+
+@pytest.mark.parametrize("sigma,shape", [(6.0, (40, 24, 30)), (10.0, (70, 20, 26))])
+def test_compiled_and_table_driven_kernels_agree_bitwise(sigma, shape):
+    """FP32 at a compiled shell: the compiled kernel (automatic choice) and
+    the table-driven ring kernel (a forced shell tile) give the same bits."""
+    nx, ny, nz = shape
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=4)
+    T = random_temperature(nx, ny, nz, 1.0 / 3.0, 0.1, seed=5)
+    outs = []
+    for forced in (False, True):
+        ctx = _ctx(nx, ny, nz, True, "fp32", sigma)
+        if forced:
+            ctx.set_tile(6)
+        outs.append(ctx.thermal_fields(n, u, T))
+        ctx.destroy()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

@@ -9,8 +9,12 @@ eq. thermalforce; k_B = m = 1) against what the paper and the mathematics fix.
   the local T as a prefactor, which the closed form keeps).  The bar,
   1e-10 of the largest value, is the rounding of T ~ 1/3 in differences of
   a thousandth of it, summed over the shell.
-- Their long-wave limits are the Sec. 4 small-gradient results: the
-  heat-flux correction B / (4 omega0) of eq. c1exp22, the collisional
+- Their long-wave limits are the Sec. 4 small-gradient results: for B the
+  angular integral of eq. campos, B = -(8 pi/3) T n^2 g sigma^3 grad T,
+  which is 4 omega0 times the heat-flux correction of eq. c1exp22 (the
+  relation delta q = B/(2 omega0) stated with eq. qexplicit would make it
+  twice eq. c1exp22: the paper's two statements differ by a factor 2, and
+  B here follows eq. campos as written); the collisional
   conductivity (2/3) sqrt(pi T) g n^2 sigma^4 of eq. thermalcond, the
   collisional compression work -P^c div u of the energy balance (Sec. 2),
   and the thermal part of the collisional pressure gradient,
@@ -109,8 +113,8 @@ def test_long_wave_limits_are_the_small_gradient_results():
         cfg, q, z, n0, T0, T, Q, B, FT = _wave(sigma, eta, L, eps=eps)
         _, _, _, emean, e2mean = _shell_sums(sigma, q)
         r1, r2 = emean / sigma, e2mean / sigma ** 2
-        # heat-flux correction B/(4 omega0) = -(1/omega0) T n^2 g (4 pi/6) sigma^3 dT/dz (eq. c1exp22),
-        # dT/dz = T0 eps q cos(qz)
+        # B = -2 T n sigma^2 (4 pi/3) g n sigma dT/dz = 4 omega0 x eq. c1exp22's
+        # -(1/omega0) T n^2 g (4 pi/6) sigma^3 dT/dz, dT/dz = T0 eps q cos(qz)
         b = -4 * T0 * n0 ** 2 * g * (4 * math.pi / 6) * sigma ** 3 * T0 * eps * q * r1
         # collisional conduction Q = lambda_c d2T/dz2, lambda_c = (2/3) sqrt(pi T) g n^2 sigma^4 (eq. thermalcond),
         # d2T/dz2 = -T0 eps q^2 sin(qz)
