@@ -447,9 +447,6 @@ def main():
             sys.exit("--transport takes a comma list of bulk, sound, slit")
         print(json.dumps(transport_bench(parts)), flush=True)
         return
-    if args.thermal:
-        print(json.dumps(thermal_bench(w, args.precision)), flush=True)
-        return
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
@@ -458,6 +455,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.thermal:
+        print(json.dumps(thermal_bench(w, args.precision)), flush=True)
+        return
 
     print(f"bench: {w.name}, {args.precision}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
     r = timed_run(w, args.precision, args.steps, args.warmup, stream)
