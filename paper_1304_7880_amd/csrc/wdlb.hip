@@ -886,6 +886,15 @@ wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, co
         HIPCHK(c, hipMemcpyAsync(c->u_rd, w.data(), 3 * N * sizeof(R), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    // the call raises and reads its own flag word (the first per-plane word,
+    // which only stacked lattices use), so that a step's instability not yet
+    // reported by a synchronising call survives it
+    struct FlagSwap {
+        wdlb_ctx *c;
+        int *saved;
+        ~FlagSwap() { c->flag = saved; }
+    } swap{c, c->flag};
+    c->flag = swap.saved + 1;
     HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     const dim3 grid = grid1(g.N, 256);
     hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (R *)c->rho_p);

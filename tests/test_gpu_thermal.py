@@ -204,3 +204,36 @@ def test_compiled_and_table_driven_kernels_agree_bitwise(sigma, shape):
         ctx.destroy()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_step_instability_survives_a_thermal_call():
+    """A step that met a packing fraction >= 1 is still reported by the next
+    synchronising call after a (successful) thermal-field evaluation."""
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma = 8, 8, 8, 4.0
+    ctx = _ctx(nx, ny, nz, True, "fp32", sigma)
+    ctx.init_fields(np.full(nx * ny * nz, packing_to_density(1.2, sigma)), np.zeros(3 * nx * ny * nz))
+    ctx.step(1)
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=9)
+    Q, _, _ = ctx.thermal_fields(n, u, random_temperature(nx, ny, nz, 1.0 / 3.0, 0.1, seed=10))
+    assert np.isfinite(Q).all()
+    with pytest.raises(wdlb.WdlbError) as e:
+        ctx.sync()
+    assert e.value.status == wdlb.E_UNSTABLE
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-5), ("bf16_local64", 2e-5)])
+def test_thermal_fields_bf16_storage_modes(prec, tol):
+    """The BF16 storage modes keep FP32 per-step arrays: the thermal fields
+    are those of FP32."""
+    nx, ny, nz, sigma, walls = 37, 21, 19, 4.0, True
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=11)
+    T = random_temperature(nx, ny, nz, 1.0 / 3.0, 0.1, seed=12)
+    cfg = ref.Config(nx, ny, nz, walls, sigma, 1.0)
+    Q_o, B_o, FT_o = ref.thermal(cfg, n, ref.nbar(cfg, n), u, T)
+    ctx = _ctx(nx, ny, nz, walls, prec, sigma)
+    Q_g, B_g, FT_g = ctx.thermal_fields(n, u, T)
+    ctx.destroy()
+    e = (_rel(Q_g, Q_o), _rel(B_g, B_o), _rel(FT_g, FT_o))
+    assert max(e) < tol, e
