@@ -310,9 +310,10 @@ THERMAL_FLOPS_PER_OFFSET = 22.0
 
 def thermal_bench(w, prec, reps=5):
     """The thermal fields at seeded random n, u, T on workload w: k_thermal's
-    mean duration by HIP events over reps calls, its rate against the FP32
-    vector peak, and the host-inclusive time of one call (the fields cross
-    PCIe both ways)."""
+    mean duration by HIP events over reps calls and its rate against the FP32
+    vector peak; the whole device-resident call (wdlb_thermal_fields_device:
+    pads, contact values, thermal kernel); and the host-inclusive time of one
+    call from host arrays (the fields cross PCIe both ways)."""
     from paper_1304_7880_amd import wdlb
     from paper_1304_7880_amd.workloads import random_fields, random_temperature
     n, u = random_fields(w.nx, w.ny, w.nz, w.n0, 0.05, 0.01, seed=1)
@@ -326,8 +327,23 @@ def thermal_bench(w, prec, reps=5):
     call_s = (time.perf_counter() - t0) / reps
     ms, cnt = ctx.profile_read()["k_thermal"]
     ctx.profile(False)
+    # the device-resident call (fields already in HBM): pads, contact values
+    # and the thermal kernel, timed by HIP events on the context's stream
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dn, du, dT = (torch.tensor(a, dtype=dt, device="cuda") for a in (n, u, T))
+    outs = [torch.empty(k * w.N, dtype=dt, device="cuda") for k in (1, 3, 3)]
+    ctx.thermal_fields_device(dn, du, dT, *outs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(reps):
+        ctx.thermal_fields_device(dn, du, dT, *outs)
+    e1.record(ctx.stream)
+    ctx.sync()
+    dev_ms = e0.elapsed_time(e1) / reps
     tile, spec = ctx.get_tile()
     ctx.destroy()
+    del dn, du, dT, outs
     k_s = ms / cnt * 1e-3
     nS = shell_size(w.sigma)
     ops = THERMAL_OPS_PER_OFFSET * nS * w.N
@@ -335,6 +351,7 @@ def thermal_bench(w, prec, reps=5):
     return {"workload": w.name, "precision": PRECISION_LABEL[prec],
             "kernel": "k_thermal_s" if (spec and prec != "fp64") else "k_thermal_r",
             "avg_kernel_ms": round(ms / cnt, 5), "launches": cnt,
+            "call_ms_device": round(dev_ms, 3),
             "call_ms_host_inclusive": round(call_s * 1e3, 2),
             "roofline": {"bound": "alu", "achieved": round(ops / k_s / 1e12, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(ops / k_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),

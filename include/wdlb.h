@@ -191,6 +191,19 @@ wdlb_status wdlb_read_flux(wdlb_ctx *ctx, double *j_pore, double *u_pore, double
 wdlb_status wdlb_thermal_fields(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
                                 double *h_B, double *h_FT);
 
+/* The same fields from device arrays, without host transfers: d_n[N],
+ * d_u[3N], d_T[N] in, d_Q[N], d_B[3N], d_FT[3N] out, all device memory of
+ * the storage real (double for WDLB_FP64, float in every other mode), in
+ * the node order above; owned by the caller.  Asynchronous on the
+ * context's stream (the inputs must stay valid, and the outputs are ready,
+ * when the stream reaches the call); outputs may alias inputs.  The values
+ * are not checked: a non-positive temperature gives non-finite fields, and
+ * a midpoint packing fraction >= 1 of n is reported as WDLB_E_UNSTABLE by
+ * the next synchronising call, as for a step.  WDLB_E_INVAL for a null
+ * pointer, WDLB_E_STATE for a stacked lattice. */
+wdlb_status wdlb_thermal_fields_device(wdlb_ctx *ctx, const void *d_n, const void *d_u, const void *d_T, void *d_Q,
+                                       void *d_B, void *d_FT);
+
 /* Current post-stream populations f_a (19N, FP64, order above). */
 wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);
 

@@ -767,7 +767,7 @@ size_t state_bytes(const wdlb_ctx *c)
 // else table-driven on LDS-ring tiles (32 x 8 x 2 in FP32, 32 x 8 x 1 in
 // FP64) where the two rings fit, else the cache kernel.
 template <typename R, int TZ, int NR>
-wdlb_status launch_thermal_r(wdlb_ctx *c)
+wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
     const Geom g = c->g;
     const double s = c->prm.sigma;
@@ -778,15 +778,14 @@ wdlb_status launch_thermal_r(wdlb_ctx *c)
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(32 * 8 * TZ), lds, c->stream, g, c->pad,
                            c->reach, (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(s * s), tx, ty, tz, (R *)c->rho_rd,
-                           (R *)c->F, (R *)c->A);
+                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(s * s), tx, ty, tz, Q, B, FT);
     });
 }
 
 // compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
 // sigma = 10 their two rings (75 KB) leave room for two blocks per CU
 template <int S2>
-wdlb_status launch_thermal_s(wdlb_ctx *c)
+wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
 {
     constexpr int TX = 32, TY = 16, TZ = 1, NT = TX * TY * TZ;
     constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
@@ -801,12 +800,12 @@ wdlb_status launch_thermal_s(wdlb_ctx *c)
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
                            (const V4<float> *)c->ru1_p, (const float *)c->rho_p, (const float *)c->gam_p,
-                           float(s * s), tx, ty, tz, (float *)c->rho_rd, (float *)c->F, (float *)c->A);
+                           float(s * s), tx, ty, tz, Q, B, FT);
     });
 }
 
 template <typename R>
-wdlb_status launch_thermal(wdlb_ctx *c)
+wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
     if constexpr (std::is_same<R, float>::value) {
         // the buffer loads of the contact values take a lane offset below
@@ -814,11 +813,11 @@ wdlb_status launch_thermal(wdlb_ctx *c)
         // (wdlb_set_tile >= 0) selects the table-driven kernels here too
         if (c->tile_req < 0 && 4.0 * (double)c->pad.NP < 2.0e9) {
             switch (specialised_s2(c->prm.sigma)) {
-            case 6: return launch_thermal_s<6>(c);
-            case 8: return launch_thermal_s<8>(c);
-            case 12: return launch_thermal_s<12>(c);
-            case 16: return launch_thermal_s<16>(c);
-            case 20: return launch_thermal_s<20>(c);
+            case 6: return launch_thermal_s<6>(c, Q, B, FT);
+            case 8: return launch_thermal_s<8>(c, Q, B, FT);
+            case 12: return launch_thermal_s<12>(c, Q, B, FT);
+            case 16: return launch_thermal_s<16>(c, Q, B, FT);
+            case 20: return launch_thermal_s<20>(c, Q, B, FT);
             default: break;
             }
         }
@@ -828,23 +827,23 @@ wdlb_status launch_thermal(wdlb_ctx *c)
     if (thermal_lds_bytes(32, 8, TZ, Rr, sizeof(R)) <= LDS_MAX) {
         if constexpr (TZ == 2) {
             switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1>(c);
-            case 2: return launch_thermal_r<R, TZ, 2>(c);
-            case 3: return launch_thermal_r<R, TZ, 3>(c);
-            case 4: return launch_thermal_r<R, TZ, 4>(c);
-            case 5: return launch_thermal_r<R, TZ, 5>(c);
+            case 1: return launch_thermal_r<R, TZ, 1>(c, Q, B, FT);
+            case 2: return launch_thermal_r<R, TZ, 2>(c, Q, B, FT);
+            case 3: return launch_thermal_r<R, TZ, 3>(c, Q, B, FT);
+            case 4: return launch_thermal_r<R, TZ, 4>(c, Q, B, FT);
+            case 5: return launch_thermal_r<R, TZ, 5>(c, Q, B, FT);
             default: break;
             }
         } else {
             switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1>(c);
-            case 2: return launch_thermal_r<R, TZ, 2>(c);
-            case 3: return launch_thermal_r<R, TZ, 3>(c);
-            case 4: return launch_thermal_r<R, TZ, 4>(c);
-            case 5: return launch_thermal_r<R, TZ, 5>(c);
-            case 6: return launch_thermal_r<R, TZ, 6>(c);
-            case 7: return launch_thermal_r<R, TZ, 7>(c);
-            case 8: return launch_thermal_r<R, TZ, 8>(c);
+            case 1: return launch_thermal_r<R, TZ, 1>(c, Q, B, FT);
+            case 2: return launch_thermal_r<R, TZ, 2>(c, Q, B, FT);
+            case 3: return launch_thermal_r<R, TZ, 3>(c, Q, B, FT);
+            case 4: return launch_thermal_r<R, TZ, 4>(c, Q, B, FT);
+            case 5: return launch_thermal_r<R, TZ, 5>(c, Q, B, FT);
+            case 6: return launch_thermal_r<R, TZ, 6>(c, Q, B, FT);
+            case 7: return launch_thermal_r<R, TZ, 7>(c, Q, B, FT);
+            case 8: return launch_thermal_r<R, TZ, 8>(c, Q, B, FT);
             default: break;
             }
         }
@@ -855,24 +854,45 @@ wdlb_status launch_thermal(wdlb_ctx *c)
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL((k_thermal<R>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, c->pad,
                            (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, (R *)c->rho_rd, (R *)c->F,
-                           (R *)c->A);
+                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, Q, B, FT);
     });
 }
 
-// Thermal fields at given n, u, T (wdlb_thermal_fields).  The inputs go to
-// per-step arrays that the next step rewrites before it reads them: n to
-// jx, T to jy, u to u_rd; then n is padded into the density array, the
-// contact values are formed by the step's density kernel, (n, u) is padded
-// into the (rho, u1) array and T over the padded density.  Q goes to rho_rd,
-// B to F and F^T to the first three planes of A.  The state is untouched.
+// Thermal fields at given n, u, T.  The device part (thermal_launch) reads
+// n[N], u[3N], T[N] and writes Q[N], B[3N], F^T[3N] (arrays of the storage
+// real) through the per-step arrays that the next step rewrites before it
+// reads them: n is padded into the density array, the step's density kernel
+// forms the contact values from it, (n, u) is padded into the (rho, u1)
+// array and T over the density array.  The state is untouched.
 template <typename R>
-wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
-                                  double *h_B, double *h_FT)
+wdlb_status thermal_launch(wdlb_ctx *c, const R *n, const R *u, const R *T, R *Q, R *B, R *FT)
 {
     const Geom g = c->g;
     const Pad pd = c->pad;
-    const size_t N = (size_t)g.N;
+    const dim3 grid = grid1(g.N, 256);
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, n, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    const int prof = c->prof;
+    c->prof = prof & (1 << K_THERMAL);  // only k_thermal is timed here
+    wdlb_status st = launch_density<R>(c);
+    c->prof = prof;
+    if (st != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_pad_ru<R>), grid, dim3(256), 0, c->stream, g, pd, n, u, (V4<R> *)c->ru1_p);
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, T, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    st = launch_thermal<R>(c, Q, B, FT);
+    if (st != WDLB_OK) return st;
+    HIPCHK(c, hipGetLastError());
+    return WDLB_OK;
+}
+
+// host fields: n to jx, T to jy, u to u_rd (FP64 -> storage real), Q to
+// rho_rd, B to F and F^T to the first three planes of A, then back
+template <typename R>
+wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *h_Q,
+                           double *h_B, double *h_FT)
+{
+    const size_t N = (size_t)c->g.N;
     {
         std::vector<R> v(N);
         for (size_t i = 0; i < N; ++i) v[i] = (R)h_n[i];
@@ -896,21 +916,9 @@ wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, co
     } swap{c, c->flag};
     c->flag = swap.saved + 1;
     HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-    const dim3 grid = grid1(g.N, 256);
-    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (R *)c->rho_p);
-    HIPCHK(c, hipGetLastError());
-    const int prof = c->prof;
-    c->prof = prof & (1 << K_THERMAL);  // only k_thermal is timed here
-    wdlb_status st = launch_density<R>(c);
-    c->prof = prof;
+    wdlb_status st = thermal_launch<R>(c, (const R *)c->jx, (const R *)c->u_rd, (const R *)c->jy, (R *)c->rho_rd,
+                                       (R *)c->F, (R *)c->A);
     if (st != WDLB_OK) return st;
-    hipLaunchKernelGGL((k_pad_ru<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (const R *)c->u_rd,
-                       (V4<R> *)c->ru1_p);
-    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jy, (R *)c->rho_p);
-    HIPCHK(c, hipGetLastError());
-    st = launch_thermal<R>(c);
-    if (st != WDLB_OK) return st;
-    HIPCHK(c, hipGetLastError());
     if ((st = check_flag(c)) != WDLB_OK) return st;
     if ((st = copy_out_r(c, c->rho_rd, N, h_Q)) != WDLB_OK) return st;
     if ((st = copy_out_r(c, c->F, 3 * N, h_B)) != WDLB_OK) return st;
@@ -987,6 +995,12 @@ wdlb_status wdlb_create(const wdlb_lattice_desc *desc, const wdlb_params *params
     c->step = 0;
     c->inited = false;
     c->tile_req = -1;
+    // no instability is pending before the first step (a sync or an
+    // asynchronous thermal-field call before init reads these words)
+    if (hipMemsetAsync(c->flag, 0, sizeof(int) * (1 + (size_t)desc->nz), c->stream) != hipSuccess) {
+        delete c;
+        return WDLB_E_HIP;
+    }
     wdlb_status st = tables(c);
     if (st != WDLB_OK) {
         delete c;
@@ -1242,6 +1256,19 @@ wdlb_status wdlb_thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_
         if (!std::isfinite(h_u[i])) return fail(c, WDLB_E_INVAL, "velocity not finite");
     if (c->store == WDLB_FP64) return thermal_fields<double>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
     return thermal_fields<float>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
+}
+
+wdlb_status wdlb_thermal_fields_device(wdlb_ctx *c, const void *d_n, const void *d_u, const void *d_T, void *d_Q,
+                                       void *d_B, void *d_FT)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (!d_n || !d_u || !d_T || !d_Q || !d_B || !d_FT) return fail(c, WDLB_E_INVAL, "null device array");
+    if (c->g.zp != nullptr) return fail(c, WDLB_E_STATE, "thermal fields of a stacked lattice");
+    if (c->store == WDLB_FP64)
+        return thermal_launch<double>(c, (const double *)d_n, (const double *)d_u, (const double *)d_T,
+                                      (double *)d_Q, (double *)d_B, (double *)d_FT);
+    return thermal_launch<float>(c, (const float *)d_n, (const float *)d_u, (const float *)d_T, (float *)d_Q,
+                                 (float *)d_B, (float *)d_FT);
 }
 
 static wdlb_status planes(wdlb_ctx *c, std::vector<double> &out)

@@ -30,7 +30,7 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 
 SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_create_static", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
-           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
+           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_thermal_fields_device", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
            "wdlb_get_tile", "wdlb_set_graphs", "wdlb_last_error", "wdlb_destroy",
            "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.wdlb_read_flux.argtypes = [vp, dp, dp, dp]
     L.wdlb_read_populations.argtypes = [vp, dp]
     L.wdlb_thermal_fields.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    L.wdlb_thermal_fields_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wdlb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.wdlb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.wdlb_load_state.argtypes = [vp, vp, C.c_size_t]
@@ -265,6 +266,20 @@ class Context:
         self._chk(self._L.wdlb_thermal_fields(self.h, _ptr(n), _ptr(u), _ptr(T), _ptr(Q), _ptr(B), _ptr(FT)),
                   "thermal_fields")
         return Q, B, FT
+
+    def thermal_fields_device(self, n, u, T, Q, B, FT):
+        """wdlb_thermal_fields_device on device tensors (contiguous, on the
+        context's device, float64 in the FP64 mode and float32 otherwise):
+        n, T, Q of N values; u, B, FT of 3N.  Asynchronous on the stream."""
+        import torch
+        dt = torch.float64 if self.desc.precision == FP64 else torch.float32
+        N = self.N
+        for name, t, size in (("n", n, N), ("u", u, 3 * N), ("T", T, N), ("Q", Q, N), ("B", B, 3 * N),
+                              ("FT", FT, 3 * N)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == size):
+                raise ValueError(f"{name}: a contiguous {dt} device tensor of {size} values is required")
+        self._chk(self._L.wdlb_thermal_fields_device(self.h, n.data_ptr(), u.data_ptr(), T.data_ptr(), Q.data_ptr(),
+                                                     B.data_ptr(), FT.data_ptr()), "thermal_fields_device")
 
     def read_populations(self):
         f = np.zeros(19 * self.N)

@@ -250,6 +250,20 @@ def test_checkpoint_resume_and_determinism():
         x.destroy()
 
 
+def test_new_context_has_no_pending_instability():
+    """A context created on reused device memory (the torch allocator hands
+    back the block of an unstable context just destroyed) reports nothing
+    before its first step."""
+    nx, ny, nz = 8, 8, 8
+    ctx = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (0, 0, 0))
+    ctx.init_fields(np.full(nx * ny * nz, packing_to_density(1.2, 4.0)), np.zeros(3 * nx * ny * nz))
+    ctx.step(1)
+    ctx.destroy()
+    ctx2 = _ctx(nx, ny, nz, True, "fp32", 4.0, 0.3, 1.0, (0, 0, 0))
+    ctx2.sync()
+    ctx2.destroy()
+
+
 def test_instability_is_reported():
     from paper_1304_7880_amd import wdlb
     nx, ny, nz = 8, 8, 8

@@ -237,3 +237,36 @@ def test_thermal_fields_bf16_storage_modes(prec, tol):
     ctx.destroy()
     e = (_rel(Q_g, Q_o), _rel(B_g, B_o), _rel(FT_g, FT_o))
     assert max(e) < tol, e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_local64"])
+def test_device_entry_point_equals_host_entry_point(prec):
+    """wdlb_thermal_fields_device on device tensors gives the host call's
+    values bit for bit (inputs rounded to the storage real first on both
+    sides), twice in a row, the second on other fields; a packing fraction
+    >= 1 is reported by the next sync."""
+    import torch
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma = 37, 21, 19, 6.0
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = _ctx(nx, ny, nz, True, prec, sigma)
+    N = nx * ny * nz
+    for seed in (3, 4):
+        n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=seed)
+        T = random_temperature(nx, ny, nz, 1.0 / 3.0, 0.1, seed=seed + 10)
+        dn, du, dT = (torch.tensor(a, dtype=dt, device="cuda") for a in (n, u, T))
+        Q, B, FT = (torch.empty(k * N, dtype=dt, device="cuda") for k in (1, 3, 3))
+        ctx.thermal_fields_device(dn, du, dT, Q, B, FT)
+        ctx.sync()
+        # the host call on the same (rounded) inputs
+        hQ, hB, hFT = ctx.thermal_fields(dn.cpu().double().numpy(), du.cpu().double().numpy(),
+                                         dT.cpu().double().numpy())
+        assert np.array_equal(Q.cpu().double().numpy(), hQ)
+        assert np.array_equal(B.cpu().double().numpy(), hB)
+        assert np.array_equal(FT.cpu().double().numpy(), hFT)
+    dn4 = torch.full((N,), packing_to_density(1.2, sigma), dtype=dt, device="cuda")
+    ctx.thermal_fields_device(dn4, du, dT, Q, B, FT)
+    with pytest.raises(wdlb.WdlbError) as e:
+        ctx.sync()
+    assert e.value.status == wdlb.E_UNSTABLE
+    ctx.destroy()
