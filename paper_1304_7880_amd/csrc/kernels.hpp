@@ -166,15 +166,27 @@ struct TileCoord {
     int x0, y0, z0, lx, ly, lz;
 };
 
+// Within an XCD's run, tiles go x fastest while a plane of tiles is small;
+// when it holds many more tiles than an XCD runs at once (128 or more), z
+// fastest, so that the tiles in flight on an XCD are z-neighbours whose
+// stencil windows share all but TZ of their planes (read from that XCD's L2
+// instead of from HBM once per plane of tiles).
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int tiles_z)
 {
     TileCoord t;
     const int lid = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
-    const int t1 = lid / tiles_x;
-    t.x0 = (lid % tiles_x) * TX;
-    t.y0 = (t1 % tiles_y) * TY;
-    t.z0 = (t1 / tiles_y) * TZ;
+    if (tiles_x * tiles_y >= 128) {
+        const int t1 = lid / tiles_z;
+        t.z0 = (lid % tiles_z) * TZ;
+        t.x0 = (t1 % tiles_x) * TX;
+        t.y0 = (t1 / tiles_x) * TY;
+    } else {
+        const int t1 = lid / tiles_x;
+        t.x0 = (lid % tiles_x) * TX;
+        t.y0 = (t1 % tiles_y) * TY;
+        t.z0 = (t1 / tiles_y) * TZ;
+    }
     t.lx = threadIdx.x % TX;
     t.ly = (threadIdx.x / TX) % TY;
     t.lz = threadIdx.x / (TX * TY);
