@@ -166,17 +166,17 @@ struct TileCoord {
     int x0, y0, z0, lx, ly, lz;
 };
 
-// Within an XCD's run, tiles go x fastest while a plane of tiles is small;
-// when it holds many more tiles than an XCD runs at once (128 or more), z
-// fastest, so that the tiles in flight on an XCD are z-neighbours whose
-// stencil windows share all but TZ of their planes (read from that XCD's L2
-// instead of from HBM once per plane of tiles).
-template <int TX, int TY, int TZ>
+// Within an XCD's run, tiles go x fastest, so that the tiles in flight read
+// the same planes at the same time.  With ZF (kernels whose tiles are one
+// plane deep) they go z fastest once a plane of tiles is large (128 tiles or
+// more): the tiles in flight are then z-neighbours whose stencil windows
+// share all but one plane, and that column of windows fits in an XCD's L2.
+template <int TX, int TY, int TZ, bool ZF = false>
 __device__ __forceinline__ TileCoord tile_coord(int tiles_x, int tiles_y, int tiles_z)
 {
     TileCoord t;
     const int lid = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
-    if (tiles_x * tiles_y >= 128) {
+    if (ZF && tiles_x * tiles_y >= 128) {
         const int t1 = lid / tiles_z;
         t.z0 = (lid % tiles_z) * TZ;
         t.x0 = (t1 % tiles_x) * TX;

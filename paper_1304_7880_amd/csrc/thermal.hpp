@@ -229,7 +229,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V
     using SH = Shell<S2>;
     constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, NT = TX * TY * TZ, NS = TZ + 1;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const TileCoord tc = tile_coord<TX, TY, TZ>(tiles_x, tiles_y, tiles_z);
+    const TileCoord tc = tile_coord<TX, TY, TZ, TZ == 1>(tiles_x, tiles_y, tiles_z);
     const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     ShellRings<R, V4<R>, TX, TY, TZ, NR, 0> rg;
