@@ -299,7 +299,7 @@ def transport_bench(parts=("bulk", "sound", "slit")):
             "bulk": bulk, "sound": sound, "slit": slits}
 
 
-SURVEY_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
+SHELL_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
 
 # Thermal fields (Q, B_i, F^T of Sec. 3) per shell offset: dT, G = gamma rho,
 # D = G dT, k_i D (3 FMA), sum D, du (3), V = G du (3), k.V (3 FMA):
@@ -445,7 +445,7 @@ def main():
                          "one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the WDLB step on a single MI355X "
+        print("bench.py measures one GPU: the library runs the WDLB step on a single MI355X "
               "(multi-GPU halo exchange is design only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -481,7 +481,7 @@ def main():
     k_avg_s = r["shell_avg_ms"] * 1e-3
     nS = shell_size(w.sigma)
     flops36 = shell_flops_per_node(w.sigma) * w.N
-    ops26 = SURVEY_OPS_PER_OFFSET * nS * w.N
+    ops26 = SHELL_OPS_PER_OFFSET * nS * w.N
     traffic, rp_ms = profile_figures(PROFILES[args.workload])
     if args.precision != "fp32_local64":   # counters are taken in the default mode
         traffic, rp_ms = {}, {}
@@ -507,7 +507,7 @@ def main():
                      "achieved": round(ops26 / k_avg_s / 1e12, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(ops26 / k_avg_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "traffic": traffic.get(shell),
-                     "count": f"{SURVEY_OPS_PER_OFFSET:g} operations per shell offset x {nS} offsets x {w.N} nodes",
+                     "count": f"{SHELL_OPS_PER_OFFSET:g} operations per shell offset x {nS} offsets x {w.N} nodes",
                      "ops_per_launch": ops26,
                      "achieved_36flop": round(flops36 / k_avg_s / 1e12, 3),
                      "frac_36flop": round(flops36 / k_avg_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
