@@ -245,7 +245,9 @@ def transport_bench(parts=("bulk", "sound", "slit")):
     amplitude read every 10); the sound speed and longitudinal viscosity of a
     standing density wave in the same box (2000 steps, read every 2); and the
     effective viscosity of 16x16xH slits at sigma = 8 for eta = 0.11 and 0.32
-    (run to steady state)."""
+    (run to steady state); and the collisional thermal conductivity and the
+    heat-flux correction coefficient of the sigma = 8 fluid from its thermal
+    fields at two long temperature waves."""
     from paper_1304_7880_amd import transport, wdlb
     from paper_1304_7880_amd.workloads import BULK_128, BULK_ETAS
     w = BULK_128
@@ -283,6 +285,16 @@ def transport_bench(parts=("bulk", "sound", "slit")):
             row["nu_bulk"] = round(r.nu_long - 4.0 / 3.0 * row_b["nu_smdb"], 6)
         sound.append(row)
         print(json.dumps({"sound_row": row}), file=sys.stderr, flush=True)
+    thermal = []
+    for eta in (BULK_ETAS if "thermal" in parts else ()):
+        r = transport.thermal_conductivity(eta, sigma=w.sigma)
+        row = {"eta": eta, "lam_coll": round(r.lam_coll, 8), "lam_coll_over_sec4": round(r.lam_coll / r.lam_coll_sec4, 6),
+               "b_coef": round(r.b_coef, 8), "b_coef_over_sec4": round(r.b_coef / r.b_coef_sec4, 6),
+               "shell_r1": round(r.shell_r1, 6), "shell_r2": round(r.shell_r2, 6),
+               "lam_total_tau1_qexplicit": round(r.lam_total(1.0, 2.0), 8),
+               "lam_total_tau1_c1exp22": round(r.lam_total(1.0, 4.0), 8)}
+        thermal.append(row)
+        print(json.dumps({"thermal_row": row}), file=sys.stderr, flush=True)
     slits = []
     for eta in ((0.11, 0.32) if "slit" in parts else ()):
         for H in (16, 32, 64, 128, 200):
@@ -291,12 +303,13 @@ def transport_bench(parts=("bulk", "sound", "slit")):
             row = {"eta": eta, "H": H, "nu_eff": round(r.nu_eff, 6), "steps": r.steps, "converged": r.converged}
             slits.append(row)
             print(json.dumps({"slit_row": row}), file=sys.stderr, flush=True)
-    return {"metric": "kinematic viscosity (shear-wave decay; slit nu_eff = g H^2 / (12 u_pore)) and squared "
-                      "sound speed (density-wave oscillation)",
+    return {"metric": "kinematic viscosity (shear-wave decay; slit nu_eff = g H^2 / (12 u_pore)), squared "
+                      "sound speed (density-wave oscillation) and collisional thermal conductivity (thermal fields "
+                      "of a temperature wave, fp64)",
             "unit": "lattice units", "dtype": "fp32", "data": "synthetic",
             "config": {"workload": f"{w.name}, shear 5000 steps, sound 2000 steps; slits 16x16xH, sigma=8, tau=1, "
                                    "g_x=1e-6"},
-            "bulk": bulk, "sound": sound, "slit": slits}
+            "bulk": bulk, "sound": sound, "slit": slits, "thermal": thermal}
 
 
 SHELL_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
@@ -441,7 +454,8 @@ def main():
     ap.add_argument("--thermal", action="store_true",
                     help="time only the thermal-field kernel (Q, B_i, F^T) on the workload; one JSON line")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
-                    help="run the transport experiments instead (comma list of bulk, sound, slit; default all); "
+                    help="run the transport experiments instead (comma list of bulk, sound, slit, thermal; "
+                         "default bulk, sound, slit); "
                          "one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -460,8 +474,8 @@ def main():
     torch.cuda.set_device(0)
     if args.transport:
         parts = tuple(x for x in args.transport.split(",") if x)
-        if not parts or set(parts) - {"bulk", "sound", "slit"}:
-            sys.exit("--transport takes a comma list of bulk, sound, slit")
+        if not parts or set(parts) - {"bulk", "sound", "slit", "thermal"}:
+            sys.exit("--transport takes a comma list of bulk, sound, slit, thermal")
         print(json.dumps(transport_bench(parts)), flush=True)
         return
     stream = torch.cuda.current_stream()

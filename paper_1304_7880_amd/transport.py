@@ -1,9 +1,11 @@
 """Transport coefficients measured with the WDLB step: the paper's two
 experiments (Sec. 5: the bulk viscosity against packing fraction from the
 decay of a transverse shear wave, and the effective viscosity of a slit pore
-against its width from Poiseuille flow), and the longitudinal wave of the
+against its width from Poiseuille flow), the longitudinal wave of the
 small-gradient theory (Sec. 4: sound speed from the Carnahan-Starling
-equation of state, sound attenuation from the shear and bulk viscosities).
+equation of state, sound attenuation from the shear and bulk viscosities),
+and the collisional parts of the thermal conductivity of Sec. 4 from the
+thermal fields at a long temperature wave.
 
 Everything here drives the library through its C ABI (wdlb.Context) and
 post-processes FP64 plane means read back from the device; no step of the
@@ -178,3 +180,75 @@ def longitudinal_wave(eta, sigma=8.0, n=128, nxy=None, steps=2000, every=2, tau=
     q = 2.0 * math.pi / n
     return SoundWave((omega * omega + gamma * gamma) / (q * q), 2.0 * gamma / (q * q), omega, gamma, times, amps,
                      secs)
+
+
+@dataclass
+class ThermalConductivity:
+    eta: float
+    sigma: float
+    T0: float
+    n0: float
+    lam_coll: float          # collisional conductivity: Q = lam_coll d2T/dz2 at q -> 0
+    lam_coll_sec4: float     # (2/3) sqrt(pi T) g n^2 sigma^4 (Sec. 4, eq. thermalcond)
+    b_coef: float            # heat-flux correction field: B_z = -b_coef dT/dz at q -> 0
+    b_coef_sec4: float       # (8 pi/3) T n^2 g sigma^3, the angular integral of eq. campos
+    shell_r1: float          # <|e|>/sigma of the lattice shell
+    shell_r2: float          # <|e|^2>/sigma^2 of the lattice shell
+    qs: tuple                # the two wave numbers
+    lam_coll_q: tuple        # lam_coll at each
+    b_coef_q: tuple          # b_coef at each
+
+    def lam_total(self, omega0, cross=2.0):
+        """kinetic (5/2) n T / omega0 (eq. qexplicit) + cross b_coef/(cross omega0)
+        + collisional; cross = 2 follows eq. qexplicit (delta q = B/(2 omega0)),
+        cross = 4 eq. c1exp22 (the two differ by a factor 2)."""
+        return 2.5 * self.n0 * self.T0 / omega0 + self.b_coef / (cross * omega0) + self.lam_coll
+
+
+def lattice_shell(sigma):
+    """Offsets e of the lattice contact shell, sigma - 1/2 <= |e| < sigma + 1/2."""
+    R = int(math.ceil(sigma + 0.5)) + 1
+    r = np.arange(-R, R + 1)
+    e = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+    d2 = (e * e).sum(1)
+    return e[(d2 >= (sigma - 0.5) ** 2) & (d2 < (sigma + 0.5) ** 2)]
+
+
+def long_wave_limit(qs, values):
+    """value(q) = v0 + c q^2 + O(q^4): the extrapolation to q = 0 from two wave numbers."""
+    (q1, q2), (v1, v2) = qs, values
+    return (q1 * q1 * v2 - q2 * q2 * v1) / (q1 * q1 - q2 * q2)
+
+
+def thermal_conductivity(eta, sigma=8.0, lengths=(128, 256), eps=1e-4, T0=1.0 / 3.0, nxy=4,
+                         precision="fp64") -> ThermalConductivity:
+    """A temperature wave T = T0 (1 + eps sin(q z)) in a periodic nxy x nxy x L
+    box at rest and uniform density n0(eta), for each L of lengths (q = 2 pi/L):
+    the thermal fields of the library (wdlb_thermal_fields); the sin(qz)
+    harmonic of Q gives lam_coll(q) = -Q_q / (T0 eps q^2), the cos(qz) harmonic
+    of B_z gives b_coef(q) = -B_q / (T0 eps q); both extrapolated to q = 0."""
+    n0 = packing_to_density(eta, sigma)
+    qs, lam, bco = [], [], []
+    for L in lengths:
+        ctx = wdlb.Context(nxy, nxy, L, False, precision, sigma, eta, 1.0, (0.0, 0.0, 0.0))
+        z = np.arange(L, dtype=np.float64)
+        q = 2.0 * math.pi / L
+        m = nxy * nxy
+        T = np.repeat(T0 * (1.0 + eps * np.sin(q * z)), m)
+        Q, B, _ = ctx.thermal_fields(np.full(L * m, n0), np.zeros(3 * L * m), T)
+        ctx.destroy()
+        N = L * m
+        s, c = np.repeat(np.sin(q * z), m), np.repeat(np.cos(q * z), m)
+        Qq = float(Q @ s) / float(s @ s)
+        Bq = float(B[2 * N:] @ c) / float(c @ c)
+        qs.append(q)
+        lam.append(-Qq / (T0 * eps * q * q))
+        bco.append(-Bq / (T0 * eps * q))
+    g = (1.0 - eta / 2.0) / (1.0 - eta) ** 3
+    e = lattice_shell(sigma)
+    d = np.sqrt((e * e).sum(1))
+    return ThermalConductivity(eta, sigma, T0, n0, long_wave_limit(qs, lam),
+                               2.0 / 3.0 * math.sqrt(math.pi * T0) * g * n0 * n0 * sigma ** 4,
+                               long_wave_limit(qs, bco), 8.0 * math.pi / 3.0 * T0 * n0 * n0 * g * sigma ** 3,
+                               float(d.mean()) / sigma, float((d * d).mean()) / sigma ** 2, tuple(qs), tuple(lam),
+                               tuple(bco))

@@ -128,3 +128,34 @@ def test_sound_wave_matches_column_oracle(prec, tol_amp, tol_c2, tol_nu):
     assert abs(r.nu_long - nu_o) < tol_nu * nu_o
     # the Carnahan-Starling sound speed, within the lattice-shell factor at sigma = 4
     assert abs(r.c2 / transport.carnahan_starling_c2(eta) - 1) < 0.02
+
+
+@pytest.mark.parametrize("eta", [0.1, 0.35])
+def test_thermal_conductivity_matches_oracle_and_sec4(eta):
+    """The collisional conductivity and the heat-flux correction coefficient
+    measured from the GPU's thermal fields at two long temperature waves
+    (sigma = 8, FP64) equal the same procedure on the oracle's fields to
+    1e-9, and their q -> 0 limits are the Sec. 4 values times the lattice
+    shell's radius moments (<|e|^2>/sigma^2 for Q, <|e|>/sigma for B) to 2e-4."""
+    from oracle import ref
+    from paper_1304_7880_amd import transport
+    sigma = 8.0
+    _say(f"thermal conductivity sigma={sigma} eta={eta}")
+    r = transport.thermal_conductivity(eta, sigma=sigma)
+    n0 = packing_to_density(eta, sigma)
+    lam_o, b_o = [], []
+    for L, q in zip((128, 256), r.qs):
+        cfg = ref.Config(4, 4, L, False, sigma, 1.0)
+        z = np.arange(L, dtype=np.float64)
+        T = np.repeat(r.T0 * (1 + 1e-4 * np.sin(q * z)), 16)
+        rho = np.full(16 * L, n0)
+        Q, B, _ = ref.thermal(cfg, rho, ref.nbar(cfg, rho), np.zeros(48 * L), T)
+        s, c = np.repeat(np.sin(q * z), 16), np.repeat(np.cos(q * z), 16)
+        lam_o.append(-(Q @ s) / (s @ s) / (r.T0 * 1e-4 * q * q))
+        b_o.append(-(B[32 * L:] @ c) / (c @ c) / (r.T0 * 1e-4 * q))
+    for g_, o_ in zip(r.lam_coll_q + r.b_coef_q, lam_o + b_o):
+        assert abs(g_ - o_) < 1e-9 * abs(o_), (g_, o_)
+    _say(f"  lam_coll {r.lam_coll:.6e} / Sec. 4 {r.lam_coll / r.lam_coll_sec4:.6f} (shell r2 {r.shell_r2:.6f}); "
+         f"b {r.b_coef:.6e} / Sec. 4 {r.b_coef / r.b_coef_sec4:.6f} (shell r1 {r.shell_r1:.6f})")
+    assert abs(r.lam_coll / r.lam_coll_sec4 / r.shell_r2 - 1) < 2e-4
+    assert abs(r.b_coef / r.b_coef_sec4 / r.shell_r1 - 1) < 2e-4
