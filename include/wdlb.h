@@ -204,6 +204,24 @@ wdlb_status wdlb_thermal_fields(wdlb_ctx *ctx, const double *h_n, const double *
 wdlb_status wdlb_thermal_fields_device(wdlb_ctx *ctx, const void *d_n, const void *d_u, const void *d_T, void *d_Q,
                                        void *d_B, void *d_FT);
 
+/* The energy balance of Sec. 2 (eq. energyequation) for the fluid at rest
+ * (u = 0) with a fixed density, the setting in which Sec. 4 derives the
+ * thermal conductivity (eq. thermalcond), k_B = m = 1:
+ *   (3/2) n dT/dt = -div q + Q,  q = -(5/2)(n T / omega0) grad T + B / (2 omega0)
+ * (eq. qexplicit; B and Q of Sec. 3 at u = 0 with the context's sigma and
+ * shell).  Discretised by the flux through the six faces of each node (the
+ * kinetic conductivity at the mean of n T of the two nodes, the mean of
+ * B / (2 omega0)), no flux through a wall, and nsteps forward-Euler steps of
+ * length dt.  h_n[N] (> 0) and h_T[N] (> 0, updated in place) are FP64 host
+ * arrays in the node order above; omega0 > 0 the BGK rate of eq. qexplicit.
+ * Computed in the storage arithmetic.  The context's state is untouched.
+ * Errors: WDLB_E_INVAL for a bad argument or field, WDLB_E_UNSTABLE when a
+ * midpoint packing fraction of n reaches 1 (h_T is then not written).
+ * Explicit steps are stable for dt (5/3) T / omega0 <= 1/6 (the kinetic
+ * part).  Synchronises. */
+wdlb_status wdlb_conduction_at_rest(wdlb_ctx *ctx, const double *h_n, double *h_T, double omega0, double dt,
+                                    int64_t nsteps);
+
 /* Current post-stream populations f_a (19N, FP64, order above). */
 wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);
 

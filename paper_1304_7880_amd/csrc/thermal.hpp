@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_pad(Geom g, Pad p, const R *__restrict_
     for_images(g, p, x, y, z, [&](int k) { dst[k] = v; });
 }
 
-// (rho, u) from n[N] and u[3N] (component-major) into the padded V4 array
+// (rho, u) from n[N] and u[3N] (component-major; null: at rest) into the
+// padded V4 array
 template <typename R>
 __global__ __launch_bounds__(256) void k_pad_ru(Geom g, Pad p, const R *__restrict__ n, const R *__restrict__ u,
                                                 V4<R> *__restrict__ dst)
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_pad_ru(Geom g, Pad p, const R *__restri
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
-    const V4<R> v = {n[i], u[i], u[g.N + i], u[2 * g.N + i]};
+    const V4<R> v = u ? V4<R>{n[i], u[i], u[g.N + i], u[2 * g.N + i]} : V4<R>{n[i], R(0), R(0), R(0)};
     for_images(g, p, x, y, z, [&](int k) { dst[k] = v; });
 }
 
@@ -360,6 +361,51 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V
 __host__ __device__ constexpr size_t thermal_lds_bytes(int TX, int TY, int TZ, int Rr, size_t rbytes)
 {
     return (size_t)(TZ + 1) * (TX + 2 * Rr) * (TY + 2 * Rr) * 5 * rbytes;
+}
+
+// ---------------------------------------------------------------------------
+// k_conduct: one forward-Euler step of the energy balance at rest (u = 0,
+// fixed n; Sec. 2 eq. energyequation in the setting of Sec. 4's
+// conductivity), T_new = T + dt (-div q + Q) / ((3/2) n), with the heat flux
+// of eq. qexplicit through the six faces of the node: kinetic
+// -kin * mean(n T) * (T(r + e) - T(r)), kin = 5 / (2 omega0), plus the mean
+// of delta q = cq B, cq = 1 / (2 omega0), at the two nodes; no flux through a
+// wall.  T and n come padded (periodic images in place), B unpadded.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_conduct(Geom g, Pad p, const R *__restrict__ T_p,
+                                                 const V4<R> *__restrict__ ru_p, const R *__restrict__ Q,
+                                                 const R *__restrict__ B, R kin, R cq, R dt, R *__restrict__ T_out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int x, y, z;
+    if (!node_of(g, i, x, y, z)) return;
+    const long long N = g.N;
+    const int gb = pidx(p, x, y, z);
+    const R T0 = T_p[gb], n0 = ru_p[gb].x, nT0 = n0 * T0;
+    const int dp[3] = {1, p.PX, p.PXY};
+    // unpadded neighbour indices (periodic wrap; at a wall the face is closed)
+    const int xp = x + 1 == g.nx ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+    const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+    const int zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
+    const long long row = (long long)(z * g.ny + y) * g.nx;
+    const long long ip[3] = {row + xp, (long long)(z * g.ny + yp) * g.nx + x, (long long)(zp * g.ny + y) * g.nx + x};
+    const long long im[3] = {row + xm, (long long)(z * g.ny + ym) * g.nx + x, (long long)(zm * g.ny + y) * g.nx + x};
+    R div = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R Tp = T_p[gb + dp[a]], Tm = T_p[gb - dp[a]];
+        const R nTp = ru_p[gb + dp[a]].x * Tp, nTm = ru_p[gb - dp[a]].x * Tm;
+        const R q0 = cq * B[a * N + i];
+        R fp = -kin * (R(0.5) * (nT0 + nTp)) * (Tp - T0) + R(0.5) * (q0 + cq * B[a * N + ip[a]]);
+        R fm = -kin * (R(0.5) * (nTm + nT0)) * (T0 - Tm) + R(0.5) * (cq * B[a * N + im[a]] + q0);
+        if (a == 2 && g.walls) {
+            if (z == g.nz - 1) fp = R(0);
+            if (z == 0) fm = R(0);
+        }
+        div += fp - fm;
+    }
+    T_out[i] = T0 + dt * ((-div + Q[i]) / (R(1.5) * n0));
 }
 
 }  // namespace wdlb

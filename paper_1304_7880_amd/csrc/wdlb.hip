@@ -925,6 +925,56 @@ wdlb_status thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_u, co
     return copy_out_r(c, c->A, 3 * N, h_FT);
 }
 
+// The energy balance at rest (wdlb_conduction_at_rest): n to jx, T to jy;
+// the contact values of n once; then per step T is padded over the density
+// array, the thermal fields at u = 0 go to rho_rd (Q), F (B) and A (F^T,
+// unused), and k_conduct writes the new T into jy.  The state is untouched.
+template <typename R>
+wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double omega0, double dt, int64_t nsteps)
+{
+    const Geom g = c->g;
+    const Pad pd = c->pad;
+    const size_t N = (size_t)g.N;
+    {
+        std::vector<R> v(N);
+        for (size_t i = 0; i < N; ++i) v[i] = (R)h_n[i];
+        HIPCHK(c, hipMemcpyAsync(c->jx, v.data(), N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < N; ++i) v[i] = (R)h_T[i];
+        HIPCHK(c, hipMemcpyAsync(c->jy, v.data(), N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    struct FlagSwap {  // the call's own flag word, as in thermal_fields
+        wdlb_ctx *c;
+        int *saved;
+        ~FlagSwap() { c->flag = saved; }
+    } swap{c, c->flag};
+    c->flag = swap.saved + 1;
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    const dim3 grid = grid1(g.N, 256);
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    const int prof = c->prof;
+    c->prof = prof & (1 << K_THERMAL);
+    wdlb_status st = launch_density<R>(c);
+    c->prof = prof;
+    if (st != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_pad_ru<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jx, (const R *)nullptr,
+                       (V4<R> *)c->ru1_p);
+    HIPCHK(c, hipGetLastError());
+    for (int64_t t = 0; t < nsteps; ++t) {
+        hipLaunchKernelGGL((k_pad<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->jy, (R *)c->rho_p);
+        st = launch_thermal<R>(c, (R *)c->rho_rd, (R *)c->F, (R *)c->A);
+        if (st != WDLB_OK) return st;
+        hipLaunchKernelGGL((k_conduct<R>), grid, dim3(256), 0, c->stream, g, pd, (const R *)c->rho_p,
+                           (const V4<R> *)c->ru1_p, (const R *)c->rho_rd, (const R *)c->F, R(2.5 / omega0),
+                           R(0.5 / omega0), R(dt), (R *)c->jy);
+        HIPCHK(c, hipGetLastError());
+    }
+    if ((st = check_flag(c)) != WDLB_OK) return st;
+    return copy_out_r(c, c->jy, N, h_T);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1256,6 +1306,23 @@ wdlb_status wdlb_thermal_fields(wdlb_ctx *c, const double *h_n, const double *h_
         if (!std::isfinite(h_u[i])) return fail(c, WDLB_E_INVAL, "velocity not finite");
     if (c->store == WDLB_FP64) return thermal_fields<double>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
     return thermal_fields<float>(c, h_n, h_u, h_T, h_Q, h_B, h_FT);
+}
+
+wdlb_status wdlb_conduction_at_rest(wdlb_ctx *c, const double *h_n, double *h_T, double omega0, double dt,
+                                    int64_t nsteps)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (!h_n || !h_T) return fail(c, WDLB_E_INVAL, "null field");
+    if (!(omega0 > 0.0) || !(dt >= 0.0) || !std::isfinite(dt) || nsteps < 0)
+        return fail(c, WDLB_E_INVAL, "omega0 must be positive, dt finite and non-negative, nsteps non-negative");
+    if (c->g.zp != nullptr) return fail(c, WDLB_E_STATE, "conduction on a stacked lattice");
+    const size_t N = (size_t)c->g.N;
+    for (size_t i = 0; i < N; ++i) {
+        if (!(std::isfinite(h_n[i]) && h_n[i] > 0.0)) return fail(c, WDLB_E_INVAL, "density not positive");
+        if (!(std::isfinite(h_T[i]) && h_T[i] > 0.0)) return fail(c, WDLB_E_INVAL, "temperature not positive");
+    }
+    if (c->store == WDLB_FP64) return conduction_steps<double>(c, h_n, h_T, omega0, dt, nsteps);
+    return conduction_steps<float>(c, h_n, h_T, omega0, dt, nsteps);
 }
 
 wdlb_status wdlb_thermal_fields_device(wdlb_ctx *c, const void *d_n, const void *d_u, const void *d_T, void *d_Q,

@@ -30,7 +30,7 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 
 SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_create_static", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
-           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_thermal_fields_device", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
+           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_thermal_fields_device", "wdlb_conduction_at_rest", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
            "wdlb_get_tile", "wdlb_set_graphs", "wdlb_last_error", "wdlb_destroy",
            "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.wdlb_read_populations.argtypes = [vp, dp]
     L.wdlb_thermal_fields.argtypes = [vp, dp, dp, dp, dp, dp, dp]
     L.wdlb_thermal_fields_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.wdlb_conduction_at_rest.argtypes = [vp, dp, dp, C.c_double, C.c_double, C.c_int64]
     L.wdlb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.wdlb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.wdlb_load_state.argtypes = [vp, vp, C.c_size_t]
@@ -280,6 +281,18 @@ class Context:
                 raise ValueError(f"{name}: a contiguous {dt} device tensor of {size} values is required")
         self._chk(self._L.wdlb_thermal_fields_device(self.h, n.data_ptr(), u.data_ptr(), T.data_ptr(), Q.data_ptr(),
                                                      B.data_ptr(), FT.data_ptr()), "thermal_fields_device")
+
+    def conduction_at_rest(self, n, T, omega0, dt, nsteps):
+        """T after nsteps forward-Euler steps of the energy balance at rest
+        (wdlb_conduction_at_rest) at the fixed density n (N values each)."""
+        N = self.N
+        n = np.ascontiguousarray(n, dtype=np.float64).ravel()
+        T = np.array(T, dtype=np.float64).ravel()
+        if n.size != N or T.size != N:
+            raise ValueError("field sizes do not match the lattice")
+        self._chk(self._L.wdlb_conduction_at_rest(self.h, _ptr(n), _ptr(T), float(omega0), float(dt), int(nsteps)),
+                  "conduction_at_rest")
+        return T
 
     def read_populations(self):
         f = np.zeros(19 * self.N)
