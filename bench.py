@@ -288,7 +288,10 @@ def transport_bench(parts=("bulk", "sound", "slit")):
     thermal = []
     for eta in (BULK_ETAS if "thermal" in parts else ()):
         r = transport.thermal_conductivity(eta, sigma=w.sigma)
-        row = {"eta": eta, "lam_coll": round(r.lam_coll, 8), "lam_coll_over_sec4": round(r.lam_coll / r.lam_coll_sec4, 6),
+        dcy = transport.thermal_conduction_decay(eta, sigma=w.sigma, tau=w.tau)
+        row = {"eta": eta, "lam_decay": round(dcy.lam, 8), "lam_decay_over_sec4": round(dcy.lam / dcy.lam_sec4, 6),
+               "decay_200_steps": [round(v, 6) for v in dcy.decay],
+               "lam_coll": round(r.lam_coll, 8), "lam_coll_over_sec4": round(r.lam_coll / r.lam_coll_sec4, 6),
                "b_coef": round(r.b_coef, 8), "b_coef_over_sec4": round(r.b_coef / r.b_coef_sec4, 6),
                "shell_r1": round(r.shell_r1, 6), "shell_r2": round(r.shell_r2, 6),
                "lam_total_tau1_qexplicit": round(r.lam_total(1.0, 2.0), 8),

@@ -4,8 +4,9 @@ decay of a transverse shear wave, and the effective viscosity of a slit pore
 against its width from Poiseuille flow), the longitudinal wave of the
 small-gradient theory (Sec. 4: sound speed from the Carnahan-Starling
 equation of state, sound attenuation from the shear and bulk viscosities),
-and the collisional parts of the thermal conductivity of Sec. 4 from the
-thermal fields at a long temperature wave.
+the collisional parts of the thermal conductivity of Sec. 4 from the
+thermal fields at a long temperature wave, and the whole conductivity from
+the decay of that wave under the energy balance at rest.
 
 Everything here drives the library through its C ABI (wdlb.Context) and
 post-processes FP64 plane means read back from the device; no step of the
@@ -252,3 +253,46 @@ def thermal_conductivity(eta, sigma=8.0, lengths=(128, 256), eps=1e-4, T0=1.0 / 
                                long_wave_limit(qs, bco), 8.0 * math.pi / 3.0 * T0 * n0 * n0 * g * sigma ** 3,
                                float(d.mean()) / sigma, float((d * d).mean()) / sigma ** 2, tuple(qs), tuple(lam),
                                tuple(bco))
+
+
+@dataclass
+class ConductionDecay:
+    eta: float
+    qs: tuple                # wave numbers 2 pi / L
+    lam_q: tuple             # -(3 n / 2) r / q^2 with r the measured per-step rate of the wave
+    lam: float               # extrapolated to q = 0
+    lam_sec4: float          # (5/2) n T / omega0 + (8 pi/3) T n^2 g sigma^3 r1 / (2 omega0)
+                             # + (2/3) sqrt(pi T) g n^2 sigma^4 r2 (Sec. 4, with the shell's moments)
+    decay: tuple             # A(steps) / A(0) of each wave
+
+
+def thermal_conduction_decay(eta, sigma=8.0, lengths=(128, 256), eps=1e-4, T0=1.0 / 3.0, tau=1.0, dt=0.1,
+                             steps=200, nxy=4, precision="fp64") -> ConductionDecay:
+    """A temperature wave T0 (1 + eps sin(q z)) in a periodic nxy x nxy x L box
+    at rest and uniform density, advanced by the energy balance at rest
+    (wdlb_conduction_at_rest, steps forward-Euler steps of dt); the per-step
+    rate r of its amplitude gives lambda(q) = -(3 n / 2) r / q^2, extrapolated
+    to q = 0 from the lengths."""
+    n0 = packing_to_density(eta, sigma)
+    omega0 = 1.0 / tau
+    qs, lam, dec = [], [], []
+    for L in lengths:
+        ctx = wdlb.Context(nxy, nxy, L, False, precision, sigma, eta, tau, (0.0, 0.0, 0.0))
+        z = np.arange(L, dtype=np.float64)
+        q = 2.0 * math.pi / L
+        m = nxy * nxy
+        s = np.repeat(np.sin(q * z), m)
+        T = T0 * (1.0 + eps * s)
+        Tk = ctx.conduction_at_rest(np.full(L * m, n0), T, omega0, dt, steps)
+        ctx.destroy()
+        a0, ak = float((T - T0) @ s), float((Tk - T0) @ s)
+        r = ((ak / a0) ** (1.0 / steps) - 1.0) / dt
+        qs.append(q)
+        lam.append(-1.5 * n0 * r / (q * q))
+        dec.append(ak / a0)
+    g = (1.0 - eta / 2.0) / (1.0 - eta) ** 3
+    d = np.sqrt((lattice_shell(sigma) ** 2).sum(1))
+    r1, r2 = float(d.mean()) / sigma, float((d * d).mean()) / sigma ** 2
+    sec4 = (2.5 * n0 * T0 / omega0 + 8.0 * math.pi / 3.0 * T0 * n0 * n0 * g * sigma ** 3 * r1 / (2.0 * omega0)
+            + 2.0 / 3.0 * math.sqrt(math.pi * T0) * g * n0 * n0 * sigma ** 4 * r2)
+    return ConductionDecay(eta, tuple(qs), tuple(lam), long_wave_limit(qs, lam), sec4, tuple(dec))

@@ -159,3 +159,16 @@ def test_thermal_conductivity_matches_oracle_and_sec4(eta):
          f"b {r.b_coef:.6e} / Sec. 4 {r.b_coef / r.b_coef_sec4:.6f} (shell r1 {r.shell_r1:.6f})")
     assert abs(r.lam_coll / r.lam_coll_sec4 / r.shell_r2 - 1) < 2e-4
     assert abs(r.b_coef / r.b_coef_sec4 / r.shell_r1 - 1) < 2e-4
+
+
+def test_conduction_decay_gives_the_sec4_conductivity():
+    """The energy balance at rest on the GPU (FP64, sigma = 8, eta = 0.25,
+    tau = 1): the decay of two long temperature waves, extrapolated to q -> 0,
+    gives Sec. 4's conductivity -- kinetic (5/2) n T / omega0, cross-over
+    b/(2 omega0) (eq. qexplicit) and collisional, the last two with the lattice
+    shell's radius moments -- to 3e-4."""
+    from paper_1304_7880_amd import transport
+    r = transport.thermal_conduction_decay(0.25, sigma=8.0)
+    _say(f"  lambda {r.lam:.8e}  Sec. 4 {r.lam_sec4:.8e}  ratio {r.lam / r.lam_sec4:.6f}  decay {r.decay}")
+    assert all(0.0 < d < 1.0 for d in r.decay)
+    assert abs(r.lam / r.lam_sec4 - 1) < 3e-4
