@@ -244,7 +244,8 @@ wdlb_status wdlb_get_step(const wdlb_ctx *ctx, int64_t *step);
  * id k (0 .. WDLB_NKERNELS-1), the summed device time in milliseconds and
  * the number of launches timed.  wdlb_kernel_name(k) names the kernel (""
  * for an unknown id): 0 moments, 1 density, 2 meanfield, 3 shell,
- * 4 collide (the step's), 5 thermal (of wdlb_thermal_fields). */
+ * 4 collide (the step's), 5 thermal (the thermal-field kernel of
+ * wdlb_thermal_fields, wdlb_thermal_fields_device and wdlb_conduction_at_rest). */
 #define WDLB_NKERNELS 6
 wdlb_status wdlb_profile(wdlb_ctx *ctx, int32_t mask);
 wdlb_status wdlb_profile_read(wdlb_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
