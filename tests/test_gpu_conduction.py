@@ -112,3 +112,25 @@ def test_bad_input_and_state_untouched():
         ctx.destroy()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol_T,tol_dT", [("fp32_local64", 1e-6, 2e-5)])
+def test_benchmark_slit_40_steps(prec, tol_T, tol_dT):
+    """The benchmark slit's geometry (64^3 between walls, sigma = 6, eta =
+    0.35, its seeded density noise) with a seeded 10 % temperature field,
+    40 steps of dt = 0.05 at omega0 = 1/0.8, against the oracle run on the
+    same input."""
+    from paper_1304_7880_amd.workloads import SLAB_64, initial_fields
+    w = SLAB_64
+    n, _ = initial_fields(w)
+    T = random_temperature(w.nx, w.ny, w.nz, 1.0 / 3.0, 0.1, seed=31)
+    cfg = ref.Config(w.nx, w.ny, w.nz, True, w.sigma, w.tau)
+    _say(f"conduction {w.name} {prec} 40 steps")
+    To = conduction.steps(cfg, n, T, 1.0 / w.tau, 0.05, 40)
+    ctx = _ctx(w.nx, w.ny, w.nz, True, prec, w.sigma, w.eta)
+    Tg = ctx.conduction_at_rest(n, T, 1.0 / w.tau, 0.05, 40)
+    ctx.destroy()
+    eT = float(np.abs(Tg - To).max() / np.abs(To).max())
+    edT = float(np.abs((Tg - T) - (To - T)).max() / np.abs(To - T).max())
+    _say(f"  T {eT:.2e}  change of T {edT:.2e} (largest change {np.abs(To - T).max():.2e})")
+    assert eT < tol_T and edT < tol_dT, (eT, edT)
