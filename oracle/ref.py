@@ -59,6 +59,8 @@ def lib():
         L.wdlb_ref_thermal.argtypes = [cp, dp, dp, dp, dp, dp, dp, dp]
         L.wdlb_ref_init.argtypes = [cp, dp, dp, dp]
         L.wdlb_ref_step.argtypes = [cp, dp, C.c_int64]
+        L.wdlb_ref_init_thermal.argtypes = [cp, dp, dp, dp, dp]
+        L.wdlb_ref_step_thermal.argtypes = [cp, dp, dp, C.c_int64, C.c_int32]
         L.wdlb_ref_reduce.argtypes = [cp, dp, dp, dp, dp, dp]
         L.wdlb_ref_threads.restype = C.c_int
         L.wdlb_ref_set_threads.argtypes = [C.c_int]
@@ -227,3 +229,29 @@ def thermal(cfg: Config, rho, nb, v, T):
     a = lambda x: np.ascontiguousarray(x, dtype=np.float64).ravel()
     _check(lib().wdlb_ref_thermal(C.byref(c), a(rho), a(nb), a(v), a(T), Q, B, FT), "thermal")
     return Q, B, FT
+
+
+@dataclass
+class ThermalState:
+    """Oracle state of the coupled thermal flow (a hybrid reading: the
+    paper's LB scheme is isothermal): populations f (19 N) and the node
+    temperatures T (N)."""
+    cfg: Config
+    f: np.ndarray = field(default=None)
+    T: np.ndarray = field(default=None)
+
+    @classmethod
+    def from_fields(cls, cfg: Config, n, u, T) -> "ThermalState":
+        N = cfg.N
+        f = np.zeros(NQ * N)
+        a = lambda x: np.ascontiguousarray(x, dtype=np.float64).ravel()
+        c = cfg.c()
+        _check(lib().wdlb_ref_init_thermal(C.byref(c), a(n), a(u), a(T), f), "init_thermal")
+        return cls(cfg, f, np.array(T, dtype=np.float64).ravel())
+
+    def step(self, nsteps: int = 1, nsub: int = 4):
+        c = self.cfg.c()
+        _check(lib().wdlb_ref_step_thermal(C.byref(c), self.f, self.T, int(nsteps), int(nsub)), "step_thermal")
+
+    def moments(self):
+        return moments(self.cfg, self.f)

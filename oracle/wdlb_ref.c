@@ -634,3 +634,184 @@ void wdlb_ref_set_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* The coupled thermal flow (a hybrid reading of this project: the     */
+/* paper's LB scheme is isothermal, Sec. 5)                             */
+/* ------------------------------------------------------------------ */
+
+/* The temperature term of the second-order Hermite equilibrium at
+ * theta = T / kT: w_a rho (3/2) (theta - 1) (|c_a|^2 - 1). */
+static double theta_term(int a, double rho, double theta)
+{
+    double c2 = (double)(CV[a][0] * CV[a][0] + CV[a][1] * CV[a][1] + CV[a][2] * CV[a][2]);
+    return weight(a) * rho * 1.5 * (theta - 1.0) * (c2 - 1.0);
+}
+
+/* f = feq(n, u) plus the temperature term at T (N values). */
+int wdlb_ref_init_thermal(const wdlb_ref_cfg *c, const double *n, const double *u, const double *T, double *f)
+{
+    int rc = wdlb_ref_init(c, n, u, f);
+    if (rc != REF_OK) return rc;
+    long N = nnodes(c);
+    for (long i = 0; i < N; ++i)
+        for (int a = 0; a < NQ; ++a) f[(long)a * N + i] += theta_term(a, n[i], T[i] / KT);
+    return REF_OK;
+}
+
+/* The energy balance with flow (Sec. 2 eq. energyequation, k_B = m = 1):
+ *   dT/dt = -u.grad T + (2 / (3 n)) ( -div q - P:grad u + Q ),
+ *   q = -(5/2)(n T / omega0) grad T + B / (2 omega0)            (eq. qexplicit)
+ *   P_ij = n T d_ij - (n T / omega0)(d_i u_j + d_j u_i - (2/3) d_ij div u)
+ *          + (2 / omega0) A0_ij                                 (eqs. pexplicit, extrapressure)
+ * Gradients by central differences (beyond a wall: u mirrored to -u, the
+ * no-slip wall half-way; T mirrored, adiabatic); div q by face fluxes as in
+ * the conduction at rest (no flux through a wall).  One LB step dt = 1 in
+ * nsub sub-steps: the advection, work, B and Q terms at the step's start,
+ * the kinetic conduction re-evaluated every sub-step. */
+static void energy_update(const wdlb_ref_cfg *c, const double *rho, const double *u, const double *A0,
+                          const double *Q, const double *B, double *T, int nsub, double *Rfix, double *Tw)
+{
+    long N = nnodes(c);
+    double omega0 = 1.0 / c->tau;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->nz; ++z)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                long r = site(c, x, y, z);
+                double n = rho[r], Tr = T[r], gu[3][3], gT[3], divdq = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    int dx = i == 0, dy = i == 1, dz = i == 2;
+                    long sp = site(c, x + dx, y + dy, z + dz), sm = site(c, x - dx, y - dy, z - dz);
+                    for (int j = 0; j < 3; ++j) {
+                        double up = sp >= 0 ? u[(long)j * N + sp] : -u[(long)j * N + r];
+                        double um = sm >= 0 ? u[(long)j * N + sm] : -u[(long)j * N + r];
+                        gu[i][j] = 0.5 * (up - um);
+                    }
+                    double Tp = sp >= 0 ? T[sp] : Tr, Tm = sm >= 0 ? T[sm] : Tr;
+                    gT[i] = 0.5 * (Tp - Tm);
+                    double q0 = B[(long)i * N + r] / (2.0 * omega0);
+                    double fp = sp >= 0 ? 0.5 * (q0 + B[(long)i * N + sp] / (2.0 * omega0)) : 0.0;
+                    double fm = sm >= 0 ? 0.5 * (B[(long)i * N + sm] / (2.0 * omega0) + q0) : 0.0;
+                    divdq += fp - fm;
+                }
+                double divu = gu[0][0] + gu[1][1] + gu[2][2], work = 0.0, adv = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    adv += u[(long)i * N + r] * gT[i];
+                    for (int j = 0; j < 3; ++j) {
+                        double P = (i == j ? n * Tr : 0.0) -
+                                   n * Tr / omega0 * (gu[i][j] + gu[j][i] - (i == j ? 2.0 / 3.0 * divu : 0.0)) +
+                                   2.0 / omega0 * A0[(long)(3 * i + j) * N + r];
+                        work += P * gu[i][j];
+                    }
+                }
+                Rfix[r] = -adv + 2.0 / (3.0 * n) * (-divdq - work + Q[r]);
+            }
+    for (int s = 0; s < nsub; ++s) {
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < c->nz; ++z)
+            for (int y = 0; y < c->ny; ++y)
+                for (int x = 0; x < c->nx; ++x) {
+                    long r = site(c, x, y, z);
+                    double n = rho[r], Tr = T[r], div = 0.0;
+                    for (int i = 0; i < 3; ++i) {
+                        int dx = i == 0, dy = i == 1, dz = i == 2;
+                        long sp = site(c, x + dx, y + dy, z + dz), sm = site(c, x - dx, y - dy, z - dz);
+                        double fp = 0.0, fm = 0.0;
+                        if (sp >= 0) fp = -2.5 / omega0 * 0.5 * (n * Tr + rho[sp] * T[sp]) * (T[sp] - Tr);
+                        if (sm >= 0) fm = -2.5 / omega0 * 0.5 * (rho[sm] * T[sm] + n * Tr) * (Tr - T[sm]);
+                        div += fp - fm;
+                    }
+                    Tw[r] = Tr + (Rfix[r] + 2.0 / (3.0 * n) * (-div)) / nsub;
+                }
+        memcpy(T, Tw, sizeof(double) * N);
+    }
+}
+
+/* nsteps steps of the coupled thermal flow in place on f and T:
+ *   fields as in O1-O4 with theta = T / kT: F^mf scaled by theta (and u1
+ *   with it), F^v by sqrt(theta), A by theta (Sec. 3: the mean-field force
+ *   carries k_B T, the viscous force sqrt(k_B T), A_ij k_B T), plus the
+ *   thermal force F^T (eq. thermalforce) with u1;
+ *   O5 with the temperature term of the equilibrium (theta_term, relaxed
+ *   at 1/tau; the forcing and A-source as in the isothermal step);
+ *   O6 stream; then the energy balance (energy_update) with the step's u,
+ *   A0, Q and B.  At T = kT everywhere the populations take the isothermal
+ *   step exactly. */
+int wdlb_ref_step_thermal(const wdlb_ref_cfg *c, double *f, double *T, int64_t nsteps, int32_t nsub)
+{
+    if (!cfg_ok(c) || nsteps < 0 || nsub < 1) return REF_EINVAL;
+    long N = nnodes(c);
+    double *rho = malloc(sizeof(double) * N), *j = malloc(sizeof(double) * 3 * N);
+    double *nb = malloc(sizeof(double) * N), *u1 = malloc(sizeof(double) * 3 * N);
+    double *fmf = calloc(3 * N, sizeof(double)), *fv = calloc(3 * N, sizeof(double));
+    double *A = calloc(9 * N, sizeof(double)), *Q = calloc(N, sizeof(double));
+    double *B = calloc(3 * N, sizeof(double)), *FT = calloc(3 * N, sizeof(double));
+    double *u = malloc(sizeof(double) * 3 * N), *F = malloc(sizeof(double) * 3 * N);
+    double *A0 = malloc(sizeof(double) * 9 * N), *fs = malloc(sizeof(double) * NQ * N);
+    double *Rfix = malloc(sizeof(double) * N), *Tw = malloc(sizeof(double) * N);
+    int rc = REF_OK, bad = 0;
+    if (!rho || !j || !nb || !u1 || !fmf || !fv || !A || !Q || !B || !FT || !u || !F || !A0 || !fs || !Rfix || !Tw) {
+        rc = REF_ENOMEM;
+        goto out;
+    }
+    for (int64_t t = 0; t < nsteps && rc == REF_OK; ++t) {
+        wdlb_ref_moments(c, f, rho, j);
+        for (long i = 0; i < N; ++i)
+            if (!(rho[i] > 0.0) || !isfinite(rho[i]) || !(T[i] > 0.0) || !isfinite(T[i])) bad = 1;
+        if (bad) { rc = REF_EUNSTABLE; break; }
+        if (c->nonlocal) {
+            rc = wdlb_ref_nbar(c, rho, nb);
+            if (rc == REF_OK) rc = wdlb_ref_meanfield(c, rho, nb, fmf);
+            if (rc != REF_OK) break;
+        }
+        for (long i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d)
+                u1[(long)d * N + i] =
+                    j[(long)d * N + i] / rho[i] + 0.5 * (c->g[d] + T[i] / KT * fmf[(long)d * N + i]);
+        if (c->nonlocal) {
+            rc = wdlb_ref_viscous(c, rho, nb, u1, fv, A);
+            if (rc == REF_OK) rc = wdlb_ref_thermal(c, rho, nb, u1, T, Q, B, FT);
+            if (rc != REF_OK) break;
+        }
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (long i = 0; i < N; ++i) {
+            double r = rho[i], th = T[i] / KT, sq = sqrt(th);
+            double fi[NQ], fo[NQ], ui[3], Fi[3], Ai[9];
+            for (int d = 0; d < 3; ++d) {
+                Fi[d] = r * (c->g[d] + th * fmf[(long)d * N + i] + sq * fv[(long)d * N + i] + FT[(long)d * N + i]);
+                ui[d] = (j[(long)d * N + i] + 0.5 * Fi[d]) / r;
+                if (!isfinite(ui[d]) || !isfinite(Fi[d])) bad = 1;
+                u[(long)d * N + i] = ui[d];
+            }
+            double tr = A[0 * N + i] + A[4 * N + i] + A[8 * N + i];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    Ai[3 * a + b] = (c->smdb && c->nonlocal)
+                                        ? th * (0.5 * (A[(long)(3 * a + b) * N + i] + A[(long)(3 * b + a) * N + i]) -
+                                                (a == b ? tr / 3.0 : 0.0))
+                                        : 0.0;
+                    A0[(long)(3 * a + b) * N + i] = Ai[3 * a + b];
+                }
+            for (int a = 0; a < NQ; ++a) fi[a] = f[(long)a * N + i];
+            wdlb_ref_collide_node(fi, r, ui, Fi, Ai, c->tau, fo);
+            for (int a = 0; a < NQ; ++a) fs[(long)a * N + i] = fo[a] + theta_term(a, r, th) / c->tau;
+        }
+        if (bad) { rc = REF_EUNSTABLE; break; }
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < c->nz; ++z)
+            for (int y = 0; y < c->ny; ++y)
+                for (int x = 0; x < c->nx; ++x) {
+                    long r = site(c, x, y, z);
+                    for (int a = 0; a < NQ; ++a) {
+                        long src = site(c, x - CV[a][0], y - CV[a][1], z - CV[a][2]);
+                        f[(long)a * N + r] = src >= 0 ? fs[(long)a * N + src] : fs[(long)opposite(a) * N + r];
+                    }
+                }
+        energy_update(c, rho, u, A0, Q, B, T, nsub, Rfix, Tw);
+    }
+out:
+    free(rho); free(j); free(nb); free(u1); free(fmf); free(fv); free(A); free(Q); free(B); free(FT);
+    free(u); free(F); free(A0); free(fs); free(Rfix); free(Tw);
+    return rc;
+}
