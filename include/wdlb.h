@@ -47,7 +47,7 @@ typedef enum {
     WDLB_E_INVAL = 1,          /* bad argument: shape, sigma outside [1, 16], tau <= 1/2, eta outside (0,1), size */
     WDLB_E_NOMEM = 2,          /* workspace smaller than wdlb_workspace_size reports */
     WDLB_E_HIP = 3,            /* a HIP call failed; wdlb_last_error has its message */
-    WDLB_E_UNSTABLE = 4,       /* non-finite or non-positive density, or a midpoint packing fraction >= 1 */
+    WDLB_E_UNSTABLE = 4,       /* non-finite or non-positive density (or temperature), or a midpoint packing fraction >= 1 */
     WDLB_E_STATE = 5,          /* call out of order (e.g. step before init) or state buffer mismatch */
     WDLB_E_NOT_CONVERGED = 6   /* a serving request hit its step cap */
 } wdlb_status;
@@ -136,7 +136,8 @@ wdlb_status wdlb_init_fields(wdlb_ctx *ctx, const double *h_n, const double *h_u
 wdlb_status wdlb_step(wdlb_ctx *ctx, int64_t nsteps);
 
 /* Block until the stream has drained; WDLB_E_UNSTABLE if any step so far
- * met a non-finite or non-positive density or a packing fraction >= 1. */
+ * met a non-finite or non-positive density (or temperature, in
+ * wdlb_step_thermal) or a packing fraction >= 1. */
 wdlb_status wdlb_sync(wdlb_ctx *ctx);
 
 /* Fields at the current time (Sec. 5, step 4: the new density and velocity
@@ -221,6 +222,43 @@ wdlb_status wdlb_thermal_fields_device(wdlb_ctx *ctx, const void *d_n, const voi
  * part).  Synchronises. */
 wdlb_status wdlb_conduction_at_rest(wdlb_ctx *ctx, const double *h_n, double *h_T, double omega0, double dt,
                                     int64_t nsteps);
+
+/* The coupled thermal flow: the step with a local temperature T(r), a
+ * hybrid of the paper's isothermal scheme (Sec. 5) and its non-isothermal
+ * fields (Sec. 3) and energy balance (Sec. 2, eq. energyequation).  With
+ * theta = T / kT at each node the step's mean-field force and the velocity
+ * u1 of the shell sums are scaled by theta, the viscous force by
+ * sqrt(theta), A_ij by theta (Sec. 3 gives them as k_B T, sqrt(k_B T) and
+ * k_B T times the isothermal sums), the thermal force F^T (eq.
+ * thermalforce) is added to the force, and the collision relaxes towards
+ * the equilibrium plus w_a rho (3/2)(theta - 1)(|c_a|^2 - 1).  After the
+ * stream T advances by one step of
+ *   dT/dt = -u.grad T + (2/(3n)) (-div q - P:grad u + Q)
+ * with q of eq. qexplicit (omega0 = 1/tau), P of eqs. pexplicit and
+ * extrapressure (with the step's A), Q of eq. campob1; central differences
+ * (beyond a wall u mirrored to -u and T to T), div q through the six faces
+ * (none through a wall), the kinetic conduction in nsub sub-steps.
+ *
+ * FP64 storage only (the context's precision WDLB_FP64), the nonlocal
+ * fields on (smdb as set), one slit (not a stacked lattice); otherwise
+ * WDLB_E_INVAL (WDLB_E_STATE for a stacked lattice).
+ *
+ * wdlb_init_thermal: the state as wdlb_init_fields(h_n, h_u) plus the
+ * temperature term at h_T (N host doubles, each > 0 and finite, else
+ * WDLB_E_INVAL); h_T is copied to d_T, N doubles of device memory owned by
+ * the caller, which holds T from then on.  Synchronises.
+ *
+ * wdlb_step_thermal: nsteps (>= 0) coupled steps; T in d_T is updated in
+ * place, nsub >= 1 sub-steps of the conduction per step (WDLB_E_INVAL
+ * otherwise; the explicit sub-steps are stable for (5/3) T tau / nsub <=
+ * 1/6 at the largest T, the kinetic part).  Asynchronous on the context's stream like wdlb_step: a
+ * density or temperature that is not positive and finite at a step's start
+ * is reported as WDLB_E_UNSTABLE by the next synchronising call (and the
+ * state is then not meaningful).  Runs eagerly (no graph replay).  The
+ * state can be read, saved and stepped isothermally as any other; the
+ * field reads give the isothermal forces. */
+wdlb_status wdlb_init_thermal(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, double *d_T);
+wdlb_status wdlb_step_thermal(wdlb_ctx *ctx, double *d_T, int64_t nsteps, int32_t nsub);
 
 /* Current post-stream populations f_a (19N, FP64, order above). */
 wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);

@@ -15,6 +15,7 @@
 #include "../../include/wdlb.h"
 #include "kernels.hpp"
 #include "thermal.hpp"
+#include "thermal_flow.hpp"
 
 using namespace wdlb;
 
@@ -73,6 +74,7 @@ struct wdlb_ctx {
     int64_t step;
     bool inited;
     int static_dev = -1;  // device whose static workspace this context holds (wdlb_create_static), else -1
+    int shell_part = 3;   // bit 0: launch the mean-field kernel, bit 1: the viscous/SMDB kernel (the thermal step runs them apart)
     std::string err;
     // event timing of the step kernels
     int prof = 0;  // bit k: time kernel k
@@ -491,13 +493,15 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
     auto ksh = k_shell<R, TX, TY, TZ, NR, NG>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
     HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
-    wdlb_status st = launch(c, K_MEANFIELD, [&] {
-        hipLaunchKernelGGL(kmf, grid, block, lmf, c->stream, g, c->pad, c->reach, (const R *)c->rho_p,
-                           (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(-KT * s * s), R(p.g[0]),
-                           R(p.g[1]), R(p.g[2]), tx, ty, tz, (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
-    });
-    if (st != WDLB_OK) return st;
+    wdlb_status st = WDLB_OK;
+    if (c->shell_part & 1)
+        st = launch(c, K_MEANFIELD, [&] {
+            hipLaunchKernelGGL(kmf, grid, block, lmf, c->stream, g, c->pad, c->reach, (const R *)c->rho_p,
+                               (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->gam_p,
+                               (const Quad<R> *)c->quads, (const int *)c->qstart, R(-KT * s * s), R(p.g[0]),
+                               R(p.g[1]), R(p.g[2]), tx, ty, tz, (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
+        });
+    if (st != WDLB_OK || !(c->shell_part & 2)) return st;
     return launch(c, K_SHELL, [&] {
         hipLaunchKernelGGL(ksh, grid, block, lsh, c->stream, g, c->pad, c->reach, (const V4<R> *)c->ru1_p,
                            (const R *)c->gam_p, (const V4<R> *)c->fmf, (const Quad<R> *)c->quads,
@@ -522,8 +526,8 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
         const Geom g = c->g;
         const wdlb_params &p = c->prm;
         const double s = p.sigma;
-        wdlb_status st;
-        {
+        wdlb_status st = WDLB_OK;
+        if (c->shell_part & 1) {
             constexpr ShellTile T = SHELL_TILES[TIM];
             const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
             const size_t lmf = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(R), sizeof(R), true);
@@ -536,7 +540,7 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
                                    (V4<R> *)c->ru1_p, (V4<R> *)c->fmf);
             });
         }
-        if (st != WDLB_OK) return st;
+        if (st != WDLB_OK || !(c->shell_part & 2)) return st;
         constexpr ShellTile T = SHELL_TILES[TIS];
         const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
         const size_t lsh = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(V4<R>), sizeof(R), T.NG > 0);
@@ -721,6 +725,7 @@ wdlb_status check_flag(wdlb_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (f & FLAG_RHO) return fail(c, WDLB_E_UNSTABLE, "non-finite or non-positive density");
     if (f & FLAG_ETA) return fail(c, WDLB_E_UNSTABLE, "midpoint packing fraction reached 1");
+    if (f & FLAG_T) return fail(c, WDLB_E_UNSTABLE, "non-finite or non-positive temperature");
     return WDLB_OK;
 }
 
@@ -973,6 +978,95 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
     }
     if ((st = check_flag(c)) != WDLB_OK) return st;
     return copy_out_r(c, c->jy, N, h_T);
+}
+
+// One step of the coupled thermal flow (FP64 storage) on the current
+// buffers, T (N values on the device) updated in place.  The step's kernels
+// with the mean-field and viscous/SMDB kernels launched apart:
+//   k_moments, k_density, k_meanfield;
+//   k_th_u1       F^mf <- theta F^mf, u1 with it (into the (rho, u1) array);
+//   k_shell       F^v and A from that u1;
+//   k_pad         T over the density array (no longer needed);
+//   k_thermal     Q, B, F^T at (rho, u1, T) into the next parity's h array
+//                 (rewritten by the collision only after they are read);
+//   k_th_force    F = rho (g + theta F^mf + sqrt(theta) F^v + F^T), A <- theta A;
+//   k_energy_fixed  the advection, work, delta q and Q part of dT/dt (rho_rd);
+//   k_collide, then k_th_post  the temperature term relaxed at 1/tau;
+//   nsub sub-steps of k_energy_sub (u_rd between them, the last into T).
+wdlb_status thermal_flow_pass(wdlb_ctx *c, double *T, int nsub)
+{
+    using R = double;
+    const Geom g = c->g;
+    const Pad pd = c->pad;
+    const int bs = 256;
+    const dim3 grid = grid1(g.N, bs);
+    const int lgx = g.nx >= 64 ? 6 : (g.nx >= 32 ? 5 : 4);
+    const NodeTiles nt{(g.nx + (1 << lgx) - 1) >> lgx, (g.ny + (256 >> lgx) - 1) / (256 >> lgx), c->nz_run, lgx};
+    const dim3 gridt((unsigned)nt.tx * nt.ty * nt.nzr);
+    const int cur = c->cur, nxt = cur ^ 1;
+    auto *ru_in = (const V4<R> *)c->ru[cur];
+    auto *h_in = (const R *)c->h[cur];
+    const wdlb_params &p = c->prm;
+    const R kT = R(KT), omega0 = R(1.0 / p.tau);
+    const long long N = g.N;
+    R *Qf = (R *)c->h[nxt], *Bf = Qf + N, *FT = Qf + 4 * N;
+    R *Rfix = (R *)c->rho_rd, *Tmid = (R *)c->u_rd;
+    wdlb_status st = launch(c, K_MOMENTS, [&] {
+        hipLaunchKernelGGL((k_moments<R, R, R>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
+                           (R *)c->jx, (R *)c->jy, (R *)c->jz, c->flag);
+    });
+    if (st != WDLB_OK) return st;
+    if ((st = launch_density<R>(c)) != WDLB_OK) return st;
+    struct PartReset {
+        wdlb_ctx *c;
+        ~PartReset() { c->shell_part = 3; }
+    } reset{c};
+    c->shell_part = 1;
+    if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_th_u1<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, kT, (const R *)c->jx,
+                       (const R *)c->jy, (const R *)c->jz, R(p.g[0]), R(p.g[1]), R(p.g[2]), (V4<R> *)c->fmf,
+                       (V4<R> *)c->ru1_p, c->flag);
+    HIPCHK(c, hipGetLastError());
+    c->shell_part = 2;
+    if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
+    c->shell_part = 3;
+    hipLaunchKernelGGL((k_pad<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, (R *)c->rho_p);
+    HIPCHK(c, hipGetLastError());
+    if ((st = launch_thermal<R>(c, Qf, Bf, FT)) != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_th_force<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T,
+                       kT, (const V4<R> *)c->fmf, (const R *)FT, R(p.g[0]), R(p.g[1]), R(p.g[2]), (R *)c->F,
+                       (R *)c->A);
+    hipLaunchKernelGGL((k_energy_fixed<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p,
+                       (const R *)c->rho_p, (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->F,
+                       (const R *)c->A, (const R *)Qf, (const R *)Bf, omega0, Rfix);
+    HIPCHK(c, hipGetLastError());
+    st = launch(c, K_COLLIDE, [&] {
+        hipLaunchKernelGGL((k_collide<R, R, R, false>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
+                           (const R *)c->A, R(1.0 / p.tau), R(1.0 - 0.5 / p.tau), ru_in, h_in, (V4<R> *)c->ru[nxt],
+                           (R *)c->h[nxt], (R *)c->u_rd, (uint64_t)c->step);
+    });
+    if (st != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_th_post<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T, kT,
+                       R(1.0 / p.tau), (R *)c->h[nxt]);
+    for (int s = 0; s < nsub; ++s) {
+        const bool last = s == nsub - 1;
+        hipLaunchKernelGGL((k_energy_sub<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->rho_p,
+                           (const V4<R> *)c->ru1_p, (const R *)Rfix, omega0, nsub, last ? T : Tmid);
+        if (!last)
+            hipLaunchKernelGGL((k_pad<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)Tmid, (R *)c->rho_p);
+    }
+    HIPCHK(c, hipGetLastError());
+    return WDLB_OK;
+}
+
+// the coupled thermal flow runs on FP64 storage, the nonlocal fields, one
+// slit (not a stacked lattice)
+wdlb_status thermal_flow_ok(wdlb_ctx *c)
+{
+    if (c->prec != WDLB_FP64) return fail(c, WDLB_E_INVAL, "the coupled thermal flow runs in FP64 only");
+    if (!c->prm.nonlocal) return fail(c, WDLB_E_INVAL, "the coupled thermal flow needs the nonlocal fields");
+    if (c->g.zp != nullptr) return fail(c, WDLB_E_STATE, "coupled thermal flow on a stacked lattice");
+    return WDLB_OK;
 }
 
 }  // namespace
@@ -1336,6 +1430,40 @@ wdlb_status wdlb_thermal_fields_device(wdlb_ctx *c, const void *d_n, const void 
                                       (double *)d_Q, (double *)d_B, (double *)d_FT);
     return thermal_launch<float>(c, (const float *)d_n, (const float *)d_u, (const float *)d_T, (float *)d_Q,
                                  (float *)d_B, (float *)d_FT);
+}
+
+wdlb_status wdlb_init_thermal(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *d_T)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (!h_n || !h_u || !h_T || !d_T) return fail(c, WDLB_E_INVAL, "null field");
+    wdlb_status st = thermal_flow_ok(c);
+    if (st != WDLB_OK) return st;
+    const Geom g = c->g;
+    for (long long i = 0; i < g.N; ++i)
+        if (!(h_T[i] > 0.0) || !std::isfinite(h_T[i])) return fail(c, WDLB_E_INVAL, "temperature not positive");
+    if ((st = do_init(c, 0, nullptr, h_n, h_u)) != WDLB_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(d_T, h_T, (size_t)g.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL((k_th_init<double>), grid1(g.N, 256), dim3(256), 0, c->stream, g, (const V4<double> *)c->ru[0],
+                       (const double *)d_T, KT, (double *)c->h[0]);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return WDLB_OK;
+}
+
+wdlb_status wdlb_step_thermal(wdlb_ctx *c, double *d_T, int64_t nsteps, int32_t nsub)
+{
+    if (!c) return WDLB_E_INVAL;
+    if (!d_T) return fail(c, WDLB_E_INVAL, "null temperature");
+    if (nsteps < 0 || nsub < 1) return fail(c, WDLB_E_INVAL, "negative step count or sub-step count below 1");
+    wdlb_status st = thermal_flow_ok(c);
+    if (st != WDLB_OK) return st;
+    if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
+    for (int64_t t = 0; t < nsteps; ++t) {
+        if ((st = thermal_flow_pass(c, d_T, nsub)) != WDLB_OK) return st;
+        c->cur ^= 1;
+        c->step++;
+    }
+    return WDLB_OK;
 }
 
 static wdlb_status planes(wdlb_ctx *c, std::vector<double> &out)

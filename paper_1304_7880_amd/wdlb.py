@@ -30,7 +30,8 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 
 SYMBOLS = ["wdlb_workspace_size", "wdlb_create", "wdlb_create_static", "wdlb_set_params", "wdlb_init_uniform", "wdlb_init_fields",
            "wdlb_step", "wdlb_sync", "wdlb_read_fields", "wdlb_read_fields_ex", "wdlb_read_profiles",
-           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_thermal_fields_device", "wdlb_conduction_at_rest", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
+           "wdlb_read_flux", "wdlb_read_populations", "wdlb_thermal_fields", "wdlb_thermal_fields_device", "wdlb_conduction_at_rest",
+           "wdlb_init_thermal", "wdlb_step_thermal", "wdlb_state_size", "wdlb_save_state", "wdlb_load_state",
            "wdlb_get_step", "wdlb_profile", "wdlb_profile_read", "wdlb_kernel_name", "wdlb_set_tile",
            "wdlb_get_tile", "wdlb_set_graphs", "wdlb_last_error", "wdlb_destroy",
            "wdlb_server_workspace_size", "wdlb_server_create", "wdlb_server_submit", "wdlb_server_poll",
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.wdlb_thermal_fields.argtypes = [vp, dp, dp, dp, dp, dp, dp]
     L.wdlb_thermal_fields_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wdlb_conduction_at_rest.argtypes = [vp, dp, dp, C.c_double, C.c_double, C.c_int64]
+    L.wdlb_init_thermal.argtypes = [vp, dp, dp, dp, vp]
+    L.wdlb_step_thermal.argtypes = [vp, vp, C.c_int64, C.c_int32]
     L.wdlb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.wdlb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.wdlb_load_state.argtypes = [vp, vp, C.c_size_t]
@@ -175,6 +178,8 @@ class Context:
         self.params = make_params(sigma, eta, tau, g, nonlocal_, smdb)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.N = self.nx * self.ny * self.nz
+        self.device = device
+        self.T = None          # the temperature of the coupled thermal flow (device, float64)
         h = C.c_void_p()
         if static:
             self.workspace = None
@@ -293,6 +298,34 @@ class Context:
         self._chk(self._L.wdlb_conduction_at_rest(self.h, _ptr(n), _ptr(T), float(omega0), float(dt), int(nsteps)),
                   "conduction_at_rest")
         return T
+
+    def init_thermal(self, n, u, T):
+        """wdlb_init_thermal: the state at density n[N], velocity u[3N] and
+        temperature T[N] (FP64 contexts); T is held on the device in self.T."""
+        import torch
+        N = self.N
+        n = np.ascontiguousarray(n, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        if n.size != N or u.size != 3 * N or T.size != N:
+            raise ValueError("field sizes do not match the lattice")
+        if self.T is None:
+            self.T = torch.empty(N, dtype=torch.float64, device=self.device)
+        self._chk(self._L.wdlb_init_thermal(self.h, _ptr(n), _ptr(u), _ptr(T), self.T.data_ptr()), "init_thermal")
+
+    def step_thermal(self, nsteps=1, nsub=4):
+        """wdlb_step_thermal: nsteps coupled steps, the conduction in nsub
+        sub-steps each; asynchronous (sync() reports an instability)."""
+        if self.T is None:
+            raise WdlbError(E_STATE, "step_thermal: init_thermal first")
+        self._chk(self._L.wdlb_step_thermal(self.h, self.T.data_ptr(), int(nsteps), int(nsub)), "step_thermal")
+
+    def read_temperature(self):
+        """T[N] of the coupled thermal flow (FP64, host), after a sync."""
+        if self.T is None:
+            raise WdlbError(E_STATE, "read_temperature: init_thermal first")
+        self.sync()
+        return self.T.cpu().numpy().copy()
 
     def read_populations(self):
         f = np.zeros(19 * self.N)

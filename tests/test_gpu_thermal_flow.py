@@ -1,0 +1,199 @@
+"""GPU coupled thermal flow (wdlb_init_thermal / wdlb_step_thermal, FP64)
+against the FP64 oracle (ref.ThermalState) on the same seeded n, u, T.
+
+Bars: the populations and T to 1e-11 of their largest value after every
+step, and the change of T over the run to 1e-9 of its largest change (the
+shell and face sums are taken in another order, and the viscous force is
+recovered from the step's total force by a subtraction; FP64 round-off).
+Physics of the GPU path itself: at T = kT the step is the isothermal one, the
+uniform fluid at rest at another temperature stays put, and a density wave
+started on the adiabat runs at the adiabatic Carnahan-Starling sound speed.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1304_7880_amd.transport import carnahan_starling_c2, fit_damped_cosine
+from paper_1304_7880_amd.workloads import packing_to_density, random_fields, random_temperature
+
+pytestmark = pytest.mark.gpu
+
+KT = 1.0 / 3.0
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _ctx(nx, ny, nz, walls, prec, sigma, eta, tau, g=(0.0, 0.0, 0.0), nonlocal_=True, smdb=True):
+    from paper_1304_7880_amd import wdlb
+    return wdlb.Context(nx, ny, nz, walls, prec, sigma, eta, tau, g, nonlocal_, smdb)
+
+
+CASES = [
+    # (name, shape, walls, sigma, eta, tau, g, smdb, steps, nsub, T noise); the sub-steps keep the explicit
+    # conduction stable, dt (5/3) T / (omega0 nsub) <= 1/6, except in the one-sub-step case, whose grid-scale
+    # T noise grows (about 6 times a step) and is kept small for that reason
+    ("walled 21x19x13 sigma=3 (several tiles, ragged)", (21, 19, 13), True, 3.0, 0.3, 0.8, (1e-4, 2e-5, 0.0), True,
+     4, 4, 0.1),
+    ("periodic 9x7x11 sigma=4 (stencil wraps, one sub-step)", (9, 7, 11), False, 4.0, 0.25, 1.1, (0.0, 3e-5, 1e-5),
+     True, 3, 1, 1e-3),
+    ("periodic 10x9x12 sigma=4", (10, 9, 12), False, 4.0, 0.25, 1.1, (0.0, 3e-5, 1e-5), True, 3, 5, 0.1),
+    ("walled 17x5x23 sigma=6 no SMDB", (17, 5, 23), True, 6.0, 0.35, 0.8, (2e-5, 0.0, 0.0), False, 3, 4, 0.1),
+    ("walled 70x5x12 sigma=3 (per-node tiles ragged)", (70, 5, 12), True, 3.0, 0.3, 0.9, (1e-4, 0.0, 0.0), True,
+     2, 4, 0.1),
+    ("walled 23x18x19 sigma=5 (table-driven shell)", (23, 18, 19), True, 5.0, 0.3, 0.9, (1e-4, 0.0, 0.0), True, 2,
+     6, 0.1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_thermal_flow_matches_oracle(case):
+    name, (nx, ny, nz), walls, sigma, eta, tau, g, smdb, steps, nsub, noise = case
+    _say(f"thermal flow {name}")
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=41)
+    T0 = random_temperature(nx, ny, nz, KT, noise, seed=42)
+    st = ref.ThermalState.from_fields(ref.Config(nx, ny, nz, walls, sigma, tau, g, True, smdb), n, u, T0)
+    ctx = _ctx(nx, ny, nz, walls, "fp64", sigma, eta, tau, g, True, smdb)
+    ctx.init_thermal(n, u, T0)
+    for k in range(steps + 1):
+        f_g, T_g = ctx.read_populations(), ctx.read_temperature()
+        ef, eT = _rel(f_g, st.f), _rel(T_g, st.T)
+        edT = _rel(T_g - T0, st.T - T0) if k else 0.0
+        _say(f"  step {k}: f {ef:.2e}  T {eT:.2e}  change of T {edT:.2e}")
+        assert ef < 1e-11 and eT < 1e-11 and edT < 1e-9, (k, ef, eT, edT)
+        if k < steps:
+            st.step(1, nsub)
+            ctx.step_thermal(1, nsub)
+    ctx.sync()
+    ctx.destroy()
+
+
+def test_several_steps_in_one_call():
+    nx, ny, nz, sigma, eta, tau = 16, 12, 14, 4.0, 0.3, 0.9
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=43)
+    T0 = random_temperature(nx, ny, nz, KT, 0.1, seed=44)
+    st = ref.ThermalState.from_fields(ref.Config(nx, ny, nz, True, sigma, tau), n, u, T0)
+    st.step(6, 4)
+    ctx = _ctx(nx, ny, nz, True, "fp64", sigma, eta, tau)
+    ctx.init_thermal(n, u, T0)
+    ctx.step_thermal(6, 4)
+    f_g, T_g = ctx.read_populations(), ctx.read_temperature()
+    ctx.destroy()
+    assert _rel(f_g, st.f) < 1e-11 and _rel(T_g, st.T) < 1e-11 and _rel(T_g - T0, st.T - T0) < 1e-9
+
+
+def test_isothermal_temperature_gives_the_isothermal_step():
+    """At T = kT everywhere theta = 1 exactly: the populations take the
+    library's isothermal step (to the round-off of recovering F^v); T itself
+    then moves with the flow's work and Q, so one step is compared."""
+    nx, ny, nz, sigma, eta, tau, g = 21, 13, 17, 3.0, 0.3, 0.9, (1e-4, 2e-5, 0.0)
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=45)
+    a = _ctx(nx, ny, nz, True, "fp64", sigma, eta, tau, g)
+    a.init_thermal(n, u, np.full(nx * ny * nz, KT))
+    a.step_thermal(1, 2)
+    b = _ctx(nx, ny, nz, True, "fp64", sigma, eta, tau, g)
+    b.init_fields(n, u)
+    b.step(1)
+    fa, fb = a.read_populations(), b.read_populations()
+    a.destroy()
+    b.destroy()
+    assert _rel(fa, fb) < 1e-14, _rel(fa, fb)
+
+
+def test_rest_state_is_a_fixed_point():
+    nx, ny, nz, sigma = 10, 8, 12, 3.0
+    N = nx * ny * nz
+    ctx = _ctx(nx, ny, nz, False, "fp64", sigma, 0.3, 0.9)
+    ctx.init_thermal(np.full(N, packing_to_density(0.3, sigma)), np.zeros(3 * N), np.full(N, 0.41))
+    f0 = ctx.read_populations()
+    ctx.step_thermal(10, 4)
+    f1, T = ctx.read_populations(), ctx.read_temperature()
+    ctx.destroy()
+    assert np.abs(T - 0.41).max() < 1e-15 and _rel(f1, f0) < 1e-14
+
+
+def test_sound_wave_runs_at_the_adiabatic_speed():
+    """The oracle's pin of the sound speed, run on the GPU path: sigma = 8,
+    eta = 0.25, a density wave of 128 nodes started on the adiabat; c^2 within
+    1 % of kT d(nZ)/dn + (2/3) T Z^2."""
+    sigma, eta, L, eps, tau = 8.0, 0.25, 128, 1e-3, 1.0
+    N = 16 * L
+    n0 = packing_to_density(eta, sigma)
+    z = np.arange(L, dtype=np.float64)
+    s = np.sin(2 * math.pi * z / L)
+    Z = (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+    ctx = _ctx(4, 4, L, False, "fp64", sigma, eta, tau)
+    ctx.init_thermal(np.repeat(n0 * (1 + eps * s), 16), np.zeros(3 * N), np.repeat(KT * (1 + 2.0 / 3.0 * Z * eps * s), 16))
+    times, amps = [], []
+    for t in range(0, 800, 2):
+        rho, _ = ctx.read_fields()
+        times.append(t)
+        amps.append(2.0 / L * float((rho.reshape(L, 16).mean(1) / n0 - 1) @ s))
+        ctx.step_thermal(2, 4)
+    ctx.destroy()
+    times, amps = np.array(times, dtype=np.float64), np.array(amps)
+    sel = times >= 50
+    om, ga = fit_damped_cosine(times[sel], amps[sel])
+    q = 2 * math.pi / L
+    c2 = (om * om + ga * ga) / (q * q)
+    c2_ad = carnahan_starling_c2(eta) + 2.0 / 3.0 * KT * Z * Z
+    _say(f"  c^2 {c2:.6f}  adiabatic {c2_ad:.6f}  isothermal {carnahan_starling_c2(eta):.6f}")
+    assert abs(c2 / c2_ad - 1) < 0.01
+
+
+def test_bad_input():
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma = 12, 9, 10, 3.0
+    N = nx * ny * nz
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=1)
+    T = random_temperature(nx, ny, nz, KT, 0.1, seed=2)
+    for prec in ("fp32", "fp32_local64", "bf16"):
+        c = _ctx(nx, ny, nz, True, prec, sigma, 0.3, 0.9)
+        with pytest.raises(wdlb.WdlbError) as e:
+            c.init_thermal(n, u, T)
+        assert e.value.status == wdlb.E_INVAL
+        c.destroy()
+    c = _ctx(nx, ny, nz, True, "fp64", sigma, 0.3, 0.9, nonlocal_=False)
+    with pytest.raises(wdlb.WdlbError) as e:
+        c.init_thermal(n, u, T)
+    assert e.value.status == wdlb.E_INVAL
+    c.destroy()
+    c = _ctx(nx, ny, nz, True, "fp64", sigma, 0.3, 0.9)
+    for bad in (-T, T * np.nan):
+        with pytest.raises(wdlb.WdlbError) as e:
+            c.init_thermal(n, u, bad)
+        assert e.value.status == wdlb.E_INVAL
+    c.init_thermal(n, u, T)
+    for nst, nsub in ((-1, 4), (1, 0)):
+        with pytest.raises(wdlb.WdlbError) as e:
+            c.step_thermal(nst, nsub)
+        assert e.value.status == wdlb.E_INVAL
+    c.step_thermal(2, 4)
+    c.sync()
+    c.destroy()
+    assert N == T.size
+
+
+def test_negative_temperature_is_reported():
+    """A temperature that is not positive at a step's start (set from the
+    host into the device array) is reported by the next sync."""
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma = 12, 9, 10, 3.0
+    n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.0, seed=3)
+    c = _ctx(nx, ny, nz, False, "fp64", sigma, 0.3, 0.9)
+    c.init_thermal(n, u, np.full(nx * ny * nz, KT))
+    c.T[5] = -1.0
+    c.step_thermal(1, 1)
+    with pytest.raises(wdlb.WdlbError) as e:
+        c.sync()
+    assert e.value.status == wdlb.E_UNSTABLE and "temperature" in str(e.value)
+    c.destroy()
