@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CU x 4 SIMD x 64 flop/clk x 2.4 GHz)
+PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -377,6 +378,56 @@ def thermal_bench(w, prec, reps=5):
                          "frac_22flop": round(flops / k_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}}
 
 
+def thermal_flow_bench(w, steps=3, warmup=1, nsub=4):
+    """The coupled thermal flow (FP64) on workload w's lattice from its seeded
+    fields and a temperature wave across the slit, T = kT (1 + 0.05 cos(2 pi
+    z / nz)): ms per step by HIP events on the context's stream over `steps`
+    steps after `warmup`, then the library's per-kernel event timing over the
+    same number of steps (the step's kernels and k_thermal; the thermal-flow
+    kernels of their own are the rest), and the roofline of the two shell
+    kernels against the FP64 vector peak."""
+    import numpy as np
+    import torch
+    from paper_1304_7880_amd import wdlb
+    from paper_1304_7880_amd.workloads import initial_fields
+    n, u = initial_fields(w)
+    z = np.repeat(np.arange(w.nz, dtype=np.float64), w.nx * w.ny)
+    T = (1.0 / 3.0) * (1.0 + 0.05 * np.cos(2.0 * np.pi * z / w.nz))
+    del z
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, "fp64", w.sigma, w.eta, w.tau, w.g)
+    ctx.init_thermal(n, u, T)
+    del n, u
+    ctx.step_thermal(warmup, nsub)
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    ctx.step_thermal(steps, nsub)
+    e1.record(ctx.stream)
+    ctx.sync()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.profile(True)
+    ctx.step_thermal(steps, nsub)
+    kst = {k: v[0] / v[1] for k, v in ctx.profile_read().items() if v[1]}
+    ctx.profile(False)
+    Tn = ctx.read_temperature()
+    ctx.destroy()
+    # per step: one launch each, except k_thermal (one per step as well)
+    per_step = {k: round(v, 4) for k, v in kst.items()}
+    nS = shell_size(w.sigma)
+    out = {"workload": w.name, "precision": PRECISION_LABEL["fp64"], "nsub": nsub, "steps": steps,
+           "ms_per_step": round(ms, 3), "mlups": round(w.N / (ms * 1e-3) / 1e6, 2),
+           "kernels_ms_per_step": per_step,
+           "other_kernels_ms_per_step": round(ms - sum(kst.values()), 3),
+           "T_range": [float(Tn.min()), float(Tn.max())]}
+    for k, ops in (("k_shell", SHELL_OPS_PER_OFFSET), ("k_thermal", THERMAL_OPS_PER_OFFSET)):
+        if k in kst:
+            a = ops * nS * w.N / (kst[k] * 1e-3) / 1e12
+            out[f"roofline_{k}"] = {"bound": "alu", "achieved": round(a, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_VECTOR_TFLOPS, 4),
+                                    "count": f"{ops:g} operations per shell offset x {nS} offsets x {w.N} nodes"}
+    return out
+
+
 def timed_run(w, precision, steps, warmup, stream, init_fields=None):
     """Warm up, then time exactly `steps` steps of workload w between
     synchronisations, with HIP events on the library's stream around every
@@ -456,6 +507,8 @@ def main():
                     help="storage and local arithmetic of the timed lattice")
     ap.add_argument("--thermal", action="store_true",
                     help="time only the thermal-field kernel (Q, B_i, F^T) on the workload; one JSON line")
+    ap.add_argument("--thermal-flow", action="store_true",
+                    help="time only the coupled thermal flow (FP64) on the workload's lattice; one JSON line")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
                     help="run the transport experiments instead (comma list of bulk, sound, slit, thermal; "
                          "default bulk, sound, slit); "
@@ -491,6 +544,9 @@ def main():
         del src, dst
     if args.thermal:
         print(json.dumps(thermal_bench(w, args.precision)), flush=True)
+        return
+    if args.thermal_flow:
+        print(json.dumps(thermal_flow_bench(w, args.steps, args.warmup)), flush=True)
         return
 
     print(f"bench: {w.name}, {args.precision}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
