@@ -378,14 +378,15 @@ def thermal_bench(w, prec, reps=5):
                          "frac_22flop": round(flops / k_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}}
 
 
-def thermal_flow_bench(w, steps=3, warmup=1, nsub=4):
-    """The coupled thermal flow (FP64) on workload w's lattice from its seeded
-    fields and a temperature wave across the slit, T = kT (1 + 0.05 cos(2 pi
-    z / nz)): ms per step by HIP events on the context's stream over `steps`
-    steps after `warmup`, then the library's per-kernel event timing over the
-    same number of steps (the step's kernels and k_thermal; the thermal-flow
+def thermal_flow_bench(w, prec, steps=3, warmup=1, nsub=4):
+    """The coupled thermal flow on workload w's lattice in storage mode prec
+    (fp64, fp32 or fp32_local64) from its seeded fields and a temperature
+    wave across the slit, T = kT (1 + 0.05 cos(2 pi z / nz)): ms per step by
+    HIP events on the context's stream over `steps` steps after `warmup`,
+    then the library's per-kernel event timing over the same number of steps
+    (the step's kernels and the thermal-field kernel; the thermal-flow
     kernels of their own are the rest), and the roofline of the two shell
-    kernels against the FP64 vector peak."""
+    kernels against the vector peak of the storage arithmetic."""
     import numpy as np
     import torch
     from paper_1304_7880_amd import wdlb
@@ -394,7 +395,7 @@ def thermal_flow_bench(w, steps=3, warmup=1, nsub=4):
     z = np.repeat(np.arange(w.nz, dtype=np.float64), w.nx * w.ny)
     T = (1.0 / 3.0) * (1.0 + 0.05 * np.cos(2.0 * np.pi * z / w.nz))
     del z
-    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, "fp64", w.sigma, w.eta, w.tau, w.g)
+    ctx = wdlb.Context(w.nx, w.ny, w.nz, w.walls_z, prec, w.sigma, w.eta, w.tau, w.g)
     ctx.init_thermal(n, u, T)
     del n, u
     ctx.step_thermal(warmup, nsub)
@@ -409,21 +410,23 @@ def thermal_flow_bench(w, steps=3, warmup=1, nsub=4):
     ctx.step_thermal(steps, nsub)
     kst = {k: v[0] / v[1] for k, v in ctx.profile_read().items() if v[1]}
     ctx.profile(False)
+    tile, spec = ctx.get_tile()
     Tn = ctx.read_temperature()
     ctx.destroy()
-    # per step: one launch each, except k_thermal (one per step as well)
-    per_step = {k: round(v, 4) for k, v in kst.items()}
     nS = shell_size(w.sigma)
-    out = {"workload": w.name, "precision": PRECISION_LABEL["fp64"], "nsub": nsub, "steps": steps,
+    peak = PEAK_FP64_VECTOR_TFLOPS if prec == "fp64" else PEAK_FP32_VECTOR_TFLOPS
+    names = {"k_shell": "k_shell_s" if spec else "k_shell",
+             "k_thermal": "k_thermal_s" if (spec and prec != "fp64") else "k_thermal_r"}
+    out = {"workload": w.name, "precision": PRECISION_LABEL[prec], "nsub": nsub, "steps": steps,
            "ms_per_step": round(ms, 3), "mlups": round(w.N / (ms * 1e-3) / 1e6, 2),
-           "kernels_ms_per_step": per_step,
+           "kernels_ms_per_step": {k: round(v, 4) for k, v in kst.items()},
            "other_kernels_ms_per_step": round(ms - sum(kst.values()), 3),
            "T_range": [float(Tn.min()), float(Tn.max())]}
     for k, ops in (("k_shell", SHELL_OPS_PER_OFFSET), ("k_thermal", THERMAL_OPS_PER_OFFSET)):
         if k in kst:
             a = ops * nS * w.N / (kst[k] * 1e-3) / 1e12
-            out[f"roofline_{k}"] = {"bound": "alu", "achieved": round(a, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
-                                    "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_VECTOR_TFLOPS, 4),
+            out[f"roofline_{k}"] = {"kernel": names[k], "bound": "alu", "achieved": round(a, 3), "peak": peak,
+                                    "unit": "TFLOP/s", "frac": round(a / peak, 4),
                                     "count": f"{ops:g} operations per shell offset x {nS} offsets x {w.N} nodes"}
     return out
 
@@ -508,7 +511,8 @@ def main():
     ap.add_argument("--thermal", action="store_true",
                     help="time only the thermal-field kernel (Q, B_i, F^T) on the workload; one JSON line")
     ap.add_argument("--thermal-flow", action="store_true",
-                    help="time only the coupled thermal flow (FP64) on the workload's lattice; one JSON line")
+                    help="time only the coupled thermal flow on the workload's lattice (storage as --precision: "
+                         "fp64, fp32 or fp32_local64); one JSON line")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
                     help="run the transport experiments instead (comma list of bulk, sound, slit, thermal; "
                          "default bulk, sound, slit); "
@@ -546,7 +550,7 @@ def main():
         print(json.dumps(thermal_bench(w, args.precision)), flush=True)
         return
     if args.thermal_flow:
-        print(json.dumps(thermal_flow_bench(w, args.steps, args.warmup)), flush=True)
+        print(json.dumps(thermal_flow_bench(w, args.precision, args.steps, args.warmup)), flush=True)
         return
 
     print(f"bench: {w.name}, {args.precision}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)

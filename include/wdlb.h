@@ -239,26 +239,29 @@ wdlb_status wdlb_conduction_at_rest(wdlb_ctx *ctx, const double *h_n, double *h_
  * (beyond a wall u mirrored to -u and T to T), div q through the six faces
  * (none through a wall), the kinetic conduction in nsub sub-steps.
  *
- * FP64 storage only (the context's precision WDLB_FP64), the nonlocal
- * fields on (smdb as set), one slit (not a stacked lattice); otherwise
- * WDLB_E_INVAL (WDLB_E_STATE for a stacked lattice).
+ * FP64 or FP32 storage (WDLB_FP64, WDLB_FP32, WDLB_FP32_LOCAL64: T and
+ * every field in the storage real, the local kernels in the mode's
+ * arithmetic), the nonlocal fields on (smdb as set), one slit (not a
+ * stacked lattice); otherwise WDLB_E_INVAL (the BF16 modes, the local
+ * model) or WDLB_E_STATE (a stacked lattice).
  *
  * wdlb_init_thermal: the state as wdlb_init_fields(h_n, h_u) plus the
  * temperature term at h_T (N host doubles, each > 0 and finite, else
- * WDLB_E_INVAL); h_T is copied to d_T, N doubles of device memory owned by
+ * WDLB_E_INVAL); h_T is rounded to the storage real and copied to d_T, N
+ * reals of device memory (double in WDLB_FP64, float otherwise) owned by
  * the caller, which holds T from then on.  Synchronises.
  *
  * wdlb_step_thermal: nsteps (>= 0) coupled steps; T in d_T is updated in
  * place, nsub >= 1 sub-steps of the conduction per step (WDLB_E_INVAL
  * otherwise; the explicit sub-steps are stable for (5/3) T tau / nsub <=
- * 1/6 at the largest T, the kinetic part).  Asynchronous on the context's stream like wdlb_step: a
- * density or temperature that is not positive and finite at a step's start
- * is reported as WDLB_E_UNSTABLE by the next synchronising call (and the
- * state is then not meaningful).  Runs eagerly (no graph replay).  The
- * state can be read, saved and stepped isothermally as any other; the
- * field reads give the isothermal forces. */
-wdlb_status wdlb_init_thermal(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, double *d_T);
-wdlb_status wdlb_step_thermal(wdlb_ctx *ctx, double *d_T, int64_t nsteps, int32_t nsub);
+ * 1/6 at the largest T, the kinetic part).  Asynchronous on the context's
+ * stream like wdlb_step: a density or temperature that is not positive and
+ * finite at a step's start is reported as WDLB_E_UNSTABLE by the next
+ * synchronising call (and the state is then not meaningful).  Runs eagerly
+ * (no graph replay).  The state can be read, saved and stepped
+ * isothermally as any other; the field reads give the isothermal forces. */
+wdlb_status wdlb_init_thermal(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, void *d_T);
+wdlb_status wdlb_step_thermal(wdlb_ctx *ctx, void *d_T, int64_t nsteps, int32_t nsub);
 
 /* Current post-stream populations f_a (19N, FP64, order above). */
 wdlb_status wdlb_read_populations(wdlb_ctx *ctx, double *h_f);

@@ -1,7 +1,8 @@
 // thermal_flow.hpp -- the kernels that the coupled thermal flow adds to the
 // isothermal step (a hybrid reading: the paper's lattice scheme is
 // isothermal).  Device code only; included by wdlb.hip after thermal.hpp.
-// FP64 only (the viscous force is recovered from the step's total force).
+// R is the storage real (FP64 or FP32); the viscous force is recovered from
+// the step's total force, to the rounding of that total.
 //
 // With theta = T / kT at every node: the mean-field force and u1 carry
 // theta, the viscous force sqrt(theta), A theta (Sec. 3: F^mf ~ k_B T,
@@ -28,7 +29,7 @@ __device__ __forceinline__ D theta_term(int a, D rho, D theta)
 // node t holds feq(n(t), u(t)) plus the term at n(t), theta(t); a direction
 // that bounces back at a wall returns to the node itself
 template <typename R>
-__global__ __launch_bounds__(256) void k_th_init(Geom g, const V4<R> *__restrict__ ru, const R *__restrict__ T, R kT,
+__global__ __launch_bounds__(256) void k_th_init(Geom g, const V4<R> *__restrict__ ru, const R *__restrict__ T, double kT,
                                                  R *__restrict__ h)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(256) void k_th_init(Geom g, const V4<R> *__restrict
             const int ty = CY[a] ? wrap1(y + CY[a], g.ny) : y;
             t = ((long long)tz * g.ny + ty) * g.nx + tx;
         }
-        h[a * g.N + i] += theta_term<R>(a, ru[t].x, T[t] / kT);
+        // once per run: FP64 arithmetic, one rounding to the storage
+        h[a * g.N + i] = R(double(h[a * g.N + i]) + theta_term<double>(a, double(ru[t].x), double(T[t]) / kT));
     }
 }
 
@@ -219,16 +221,17 @@ __global__ __launch_bounds__(256) void k_energy_sub(Geom g, Pad p, const R *__re
 
 // after the collision: the stored post-collision populations gain the
 // temperature term relaxed at 1/tau, at the pre-collision rho and theta
-template <typename R>
+// (arithmetic D, one rounding to the storage)
+template <typename R, typename D>
 __global__ __launch_bounds__(256) void k_th_post(Geom g, Pad p, const V4<R> *__restrict__ ru1_p,
-                                                 const R *__restrict__ T, R kT, R inv_tau, R *__restrict__ h)
+                                                 const R *__restrict__ T, D kT, D inv_tau, R *__restrict__ h)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
-    const R r = ru1_p[pidx(p, x, y, z)].x, th = T[i] / kT;
+    const D r = ru1_p[pidx(p, x, y, z)].x, th = D(T[i]) / kT;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) h[a * g.N + i] += theta_term<R>(a, r, th) * inv_tau;
+    for (int a = 0; a < Q; ++a) h[a * g.N + i] = R(D(h[a * g.N + i]) + theta_term<D>(a, r, th) * inv_tau);
 }
 
 }  // namespace wdlb

@@ -980,8 +980,9 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
     return copy_out_r(c, c->jy, N, h_T);
 }
 
-// One step of the coupled thermal flow (FP64 storage) on the current
-// buffers, T (N values on the device) updated in place.  The step's kernels
+// One step of the coupled thermal flow (storage R, FP64 or FP32; the local
+// kernels in D) on the current buffers, T (N values of R on the device)
+// updated in place.  The step's kernels
 // with the mean-field and viscous/SMDB kernels launched apart:
 //   k_moments, k_density, k_meanfield;
 //   k_th_u1       F^mf <- theta F^mf, u1 with it (into the (rho, u1) array);
@@ -993,9 +994,9 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
 //   k_energy_fixed  the advection, work, delta q and Q part of dT/dt (rho_rd);
 //   k_collide, then k_th_post  the temperature term relaxed at 1/tau;
 //   nsub sub-steps of k_energy_sub (u_rd between them, the last into T).
-wdlb_status thermal_flow_pass(wdlb_ctx *c, double *T, int nsub)
+template <typename R, typename D>
+wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
 {
-    using R = double;
     const Geom g = c->g;
     const Pad pd = c->pad;
     const int bs = 256;
@@ -1012,7 +1013,7 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, double *T, int nsub)
     R *Qf = (R *)c->h[nxt], *Bf = Qf + N, *FT = Qf + 4 * N;
     R *Rfix = (R *)c->rho_rd, *Tmid = (R *)c->u_rd;
     wdlb_status st = launch(c, K_MOMENTS, [&] {
-        hipLaunchKernelGGL((k_moments<R, R, R>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
+        hipLaunchKernelGGL((k_moments<R, R, D>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
                            (R *)c->jx, (R *)c->jy, (R *)c->jz, c->flag);
     });
     if (st != WDLB_OK) return st;
@@ -1041,13 +1042,13 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, double *T, int nsub)
                        (const R *)c->A, (const R *)Qf, (const R *)Bf, omega0, Rfix);
     HIPCHK(c, hipGetLastError());
     st = launch(c, K_COLLIDE, [&] {
-        hipLaunchKernelGGL((k_collide<R, R, R, false>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
+        hipLaunchKernelGGL((k_collide<R, R, D, false>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
                            (const R *)c->A, R(1.0 / p.tau), R(1.0 - 0.5 / p.tau), ru_in, h_in, (V4<R> *)c->ru[nxt],
                            (R *)c->h[nxt], (R *)c->u_rd, (uint64_t)c->step);
     });
     if (st != WDLB_OK) return st;
-    hipLaunchKernelGGL((k_th_post<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T, kT,
-                       R(1.0 / p.tau), (R *)c->h[nxt]);
+    hipLaunchKernelGGL((k_th_post<R, D>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T,
+                       D(KT), D(1.0 / p.tau), (R *)c->h[nxt]);
     for (int s = 0; s < nsub; ++s) {
         const bool last = s == nsub - 1;
         hipLaunchKernelGGL((k_energy_sub<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->rho_p,
@@ -1059,14 +1060,38 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, double *T, int nsub)
     return WDLB_OK;
 }
 
-// the coupled thermal flow runs on FP64 storage, the nonlocal fields, one
-// slit (not a stacked lattice)
+// the coupled thermal flow runs on FP64 or FP32 storage (not the BF16
+// deviations, whose rounding and closure the added term would bypass), the
+// nonlocal fields, one slit (not a stacked lattice)
 wdlb_status thermal_flow_ok(wdlb_ctx *c)
 {
-    if (c->prec != WDLB_FP64) return fail(c, WDLB_E_INVAL, "the coupled thermal flow runs in FP64 only");
+    if (c->store == WDLB_BF16_NEQ) return fail(c, WDLB_E_INVAL, "the coupled thermal flow needs FP64 or FP32 storage");
     if (!c->prm.nonlocal) return fail(c, WDLB_E_INVAL, "the coupled thermal flow needs the nonlocal fields");
     if (c->g.zp != nullptr) return fail(c, WDLB_E_STATE, "coupled thermal flow on a stacked lattice");
     return WDLB_OK;
+}
+
+template <typename R>
+wdlb_status init_thermal(wdlb_ctx *c, const double *h_T, R *d_T)
+{
+    const Geom g = c->g;
+    std::vector<R> v((size_t)g.N);
+    for (long long i = 0; i < g.N; ++i) v[i] = (R)h_T[i];
+    HIPCHK(c, hipMemcpyAsync(d_T, v.data(), (size_t)g.N * sizeof(R), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL((k_th_init<R>), grid1(g.N, 256), dim3(256), 0, c->stream, g, (const V4<R> *)c->ru[0],
+                       (const R *)d_T, KT, (R *)c->h[0]);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return WDLB_OK;
+}
+
+wdlb_status thermal_flow_step(wdlb_ctx *c, void *d_T, int nsub)
+{
+    switch (c->prec) {
+    case WDLB_FP64: return thermal_flow_pass<double, double>(c, (double *)d_T, nsub);
+    case WDLB_FP32: return thermal_flow_pass<float, float>(c, (float *)d_T, nsub);
+    default: return thermal_flow_pass<float, double>(c, (float *)d_T, nsub);  // FP32 storage, FP64 local
+    }
 }
 
 }  // namespace
@@ -1432,25 +1457,20 @@ wdlb_status wdlb_thermal_fields_device(wdlb_ctx *c, const void *d_n, const void 
                                  (float *)d_B, (float *)d_FT);
 }
 
-wdlb_status wdlb_init_thermal(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, double *d_T)
+wdlb_status wdlb_init_thermal(wdlb_ctx *c, const double *h_n, const double *h_u, const double *h_T, void *d_T)
 {
     if (!c) return WDLB_E_INVAL;
     if (!h_n || !h_u || !h_T || !d_T) return fail(c, WDLB_E_INVAL, "null field");
     wdlb_status st = thermal_flow_ok(c);
     if (st != WDLB_OK) return st;
-    const Geom g = c->g;
-    for (long long i = 0; i < g.N; ++i)
+    for (long long i = 0; i < c->g.N; ++i)
         if (!(h_T[i] > 0.0) || !std::isfinite(h_T[i])) return fail(c, WDLB_E_INVAL, "temperature not positive");
     if ((st = do_init(c, 0, nullptr, h_n, h_u)) != WDLB_OK) return st;
-    HIPCHK(c, hipMemcpyAsync(d_T, h_T, (size_t)g.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL((k_th_init<double>), grid1(g.N, 256), dim3(256), 0, c->stream, g, (const V4<double> *)c->ru[0],
-                       (const double *)d_T, KT, (double *)c->h[0]);
-    HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return WDLB_OK;
+    if (c->store == WDLB_FP64) return init_thermal<double>(c, h_T, (double *)d_T);
+    return init_thermal<float>(c, h_T, (float *)d_T);
 }
 
-wdlb_status wdlb_step_thermal(wdlb_ctx *c, double *d_T, int64_t nsteps, int32_t nsub)
+wdlb_status wdlb_step_thermal(wdlb_ctx *c, void *d_T, int64_t nsteps, int32_t nsub)
 {
     if (!c) return WDLB_E_INVAL;
     if (!d_T) return fail(c, WDLB_E_INVAL, "null temperature");
@@ -1459,7 +1479,7 @@ wdlb_status wdlb_step_thermal(wdlb_ctx *c, double *d_T, int64_t nsteps, int32_t 
     if (st != WDLB_OK) return st;
     if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
     for (int64_t t = 0; t < nsteps; ++t) {
-        if ((st = thermal_flow_pass(c, d_T, nsub)) != WDLB_OK) return st;
+        if ((st = thermal_flow_step(c, d_T, nsub)) != WDLB_OK) return st;
         c->cur ^= 1;
         c->step++;
     }

@@ -179,7 +179,7 @@ class Context:
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.N = self.nx * self.ny * self.nz
         self.device = device
-        self.T = None          # the temperature of the coupled thermal flow (device, float64)
+        self.T = None          # the temperature of the coupled thermal flow (device, storage real)
         h = C.c_void_p()
         if static:
             self.workspace = None
@@ -301,7 +301,8 @@ class Context:
 
     def init_thermal(self, n, u, T):
         """wdlb_init_thermal: the state at density n[N], velocity u[3N] and
-        temperature T[N] (FP64 contexts); T is held on the device in self.T."""
+        temperature T[N]; T is held on the device in self.T (float64 in the
+        FP64 mode, float32 in the FP32 ones)."""
         import torch
         N = self.N
         n = np.ascontiguousarray(n, dtype=np.float64).ravel()
@@ -309,8 +310,9 @@ class Context:
         T = np.ascontiguousarray(T, dtype=np.float64).ravel()
         if n.size != N or u.size != 3 * N or T.size != N:
             raise ValueError("field sizes do not match the lattice")
-        if self.T is None:
-            self.T = torch.empty(N, dtype=torch.float64, device=self.device)
+        dt = torch.float64 if self.desc.precision == FP64 else torch.float32
+        if self.T is None or self.T.dtype != dt:
+            self.T = torch.empty(N, dtype=dt, device=self.device)
         self._chk(self._L.wdlb_init_thermal(self.h, _ptr(n), _ptr(u), _ptr(T), self.T.data_ptr()), "init_thermal")
 
     def step_thermal(self, nsteps=1, nsub=4):
@@ -321,11 +323,11 @@ class Context:
         self._chk(self._L.wdlb_step_thermal(self.h, self.T.data_ptr(), int(nsteps), int(nsub)), "step_thermal")
 
     def read_temperature(self):
-        """T[N] of the coupled thermal flow (FP64, host), after a sync."""
+        """T[N] of the coupled thermal flow (host, float64), after a sync."""
         if self.T is None:
             raise WdlbError(E_STATE, "read_temperature: init_thermal first")
         self.sync()
-        return self.T.cpu().numpy().copy()
+        return self.T.cpu().numpy().astype(np.float64)
 
     def read_populations(self):
         f = np.zeros(19 * self.N)

@@ -1,13 +1,17 @@
-"""GPU coupled thermal flow (wdlb_init_thermal / wdlb_step_thermal, FP64)
-against the FP64 oracle (ref.ThermalState) on the same seeded n, u, T.
+"""GPU coupled thermal flow (wdlb_init_thermal / wdlb_step_thermal) against
+the FP64 oracle (ref.ThermalState) on the same seeded n, u, T.
 
-Bars: the populations and T to 1e-11 of their largest value after every
-step, and the change of T over the run to 1e-9 of its largest change (the
-shell and face sums are taken in another order, and the viscous force is
-recovered from the step's total force by a subtraction; FP64 round-off).
-Physics of the GPU path itself: at T = kT the step is the isothermal one, the
-uniform fluid at rest at another temperature stays put, and a density wave
-started on the adiabat runs at the adiabatic Carnahan-Starling sound speed.
+Bars, FP64 storage: the populations and T to 1e-11 of their largest value
+after every step, and the change of T over the run to 1e-9 of its largest
+change (the shell and face sums are taken in another order, and the viscous
+force is recovered from the step's total force by a subtraction; FP64
+round-off).  FP32 storage (both local arithmetics): the populations to 1e-5
+of their largest value (FP32 storage, a few 1e-8 per step, and shell sums
+that cancel to many times the rounding of their largest term; measured
+<= 6e-7 over four steps), T to 1e-6 of itself (stored in FP32, 6e-8, and
+changed each step by the work of a velocity carrying that rounding;
+measured <= 1.5e-7) and its change to 2e-5 of the largest change (measured
+<= 9.3e-7), the bars of the FP32 conduction at rest.
 """
 import math
 import sys
@@ -55,26 +59,41 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_thermal_flow_matches_oracle(case):
+BARS = {"fp64": (1e-11, 1e-11, 1e-9), "fp32": (1e-5, 1e-6, 2e-5), "fp32_local64": (1e-5, 1e-6, 2e-5)}
+FP32_CASES = [CASES[0], CASES[2], CASES[5]]
+
+
+def _run_case(case, prec):
     name, (nx, ny, nz), walls, sigma, eta, tau, g, smdb, steps, nsub, noise = case
-    _say(f"thermal flow {name}")
+    tf, tT, tdT = BARS[prec]
+    _say(f"thermal flow {name} {prec}")
     n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=41)
     T0 = random_temperature(nx, ny, nz, KT, noise, seed=42)
     st = ref.ThermalState.from_fields(ref.Config(nx, ny, nz, walls, sigma, tau, g, True, smdb), n, u, T0)
-    ctx = _ctx(nx, ny, nz, walls, "fp64", sigma, eta, tau, g, True, smdb)
+    ctx = _ctx(nx, ny, nz, walls, prec, sigma, eta, tau, g, True, smdb)
     ctx.init_thermal(n, u, T0)
     for k in range(steps + 1):
         f_g, T_g = ctx.read_populations(), ctx.read_temperature()
         ef, eT = _rel(f_g, st.f), _rel(T_g, st.T)
         edT = _rel(T_g - T0, st.T - T0) if k else 0.0
         _say(f"  step {k}: f {ef:.2e}  T {eT:.2e}  change of T {edT:.2e}")
-        assert ef < 1e-11 and eT < 1e-11 and edT < 1e-9, (k, ef, eT, edT)
+        assert ef < tf and eT < tT and edT < tdT, (k, ef, eT, edT)
         if k < steps:
             st.step(1, nsub)
             ctx.step_thermal(1, nsub)
     ctx.sync()
     ctx.destroy()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_thermal_flow_matches_oracle(case):
+    _run_case(case, "fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_local64"])
+@pytest.mark.parametrize("case", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_thermal_flow_fp32_storage_matches_oracle(case, prec):
+    _run_case(case, prec)
 
 
 def test_several_steps_in_one_call():
@@ -109,16 +128,17 @@ def test_isothermal_temperature_gives_the_isothermal_step():
     assert _rel(fa, fb) < 1e-14, _rel(fa, fb)
 
 
-def test_rest_state_is_a_fixed_point():
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("fp32", 1e-6)])
+def test_rest_state_is_a_fixed_point(prec, tol):
     nx, ny, nz, sigma = 10, 8, 12, 3.0
     N = nx * ny * nz
-    ctx = _ctx(nx, ny, nz, False, "fp64", sigma, 0.3, 0.9)
+    ctx = _ctx(nx, ny, nz, False, prec, sigma, 0.3, 0.9)
     ctx.init_thermal(np.full(N, packing_to_density(0.3, sigma)), np.zeros(3 * N), np.full(N, 0.41))
-    f0 = ctx.read_populations()
+    f0, T0 = ctx.read_populations(), ctx.read_temperature()
     ctx.step_thermal(10, 4)
     f1, T = ctx.read_populations(), ctx.read_temperature()
     ctx.destroy()
-    assert np.abs(T - 0.41).max() < 1e-15 and _rel(f1, f0) < 1e-14
+    assert np.abs(T - T0).max() < tol * 0.41 and _rel(f1, f0) < tol
 
 
 def test_sound_wave_runs_at_the_adiabatic_speed():
@@ -156,7 +176,7 @@ def test_bad_input():
     N = nx * ny * nz
     n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=1)
     T = random_temperature(nx, ny, nz, KT, 0.1, seed=2)
-    for prec in ("fp32", "fp32_local64", "bf16"):
+    for prec in ("bf16", "bf16_local64"):
         c = _ctx(nx, ny, nz, True, prec, sigma, 0.3, 0.9)
         with pytest.raises(wdlb.WdlbError) as e:
             c.init_thermal(n, u, T)
