@@ -217,3 +217,45 @@ def test_negative_temperature_is_reported():
         c.sync()
     assert e.value.status == wdlb.E_UNSTABLE and "temperature" in str(e.value)
     c.destroy()
+
+
+@pytest.mark.parametrize("prec,tol_f,tol_T,tol_dT", [("fp32_local64", 1e-5, 1e-6, 2e-5), ("fp64", 1e-11, 1e-11, 1e-9)])
+def test_full_slab_z_only_matches_the_column_oracle(prec, tol_f, tol_T, tol_dT):
+    """The benchmark's slab (512 x 512 x 256 between walls, sigma = 10, eta =
+    0.40, tau = 0.7, g_x = 5e-7, the shells the bench runs) with seeded
+    fields that depend on z only (n: 5 %, u_x: 1e-3, T: 10 % plane by plane),
+    three coupled steps of four sub-steps: every column of the slab keeps
+    the same values, and they equal the oracle's on a 4 x 4 x 256 column of
+    the same planes (the shell sums of an x,y-homogeneous state are the
+    same on any width), sampled at 64 columns for the populations."""
+    from paper_1304_7880_amd.workloads import SLAB_LARGE as w
+    nx, ny, nz = w.nx, w.ny, w.nz
+    rng = np.random.default_rng(51)
+    n_z = w.n0 * (1 + 0.05 * rng.uniform(-1, 1, nz))
+    ux_z = 1e-3 * rng.uniform(-1, 1, nz)
+    T_z = KT * (1 + 0.1 * rng.uniform(-1, 1, nz))
+    cfg = ref.Config(4, 4, nz, True, w.sigma, w.tau, w.g)
+    uc = np.zeros(3 * cfg.N)
+    uc[:cfg.N] = np.repeat(ux_z, 16)
+    st = ref.ThermalState.from_fields(cfg, np.repeat(n_z, 16), uc, np.repeat(T_z, 16))
+    st.step(3, 4)
+    fo = st.f.reshape(19, nz, 16)[:, :, 0]
+    To = st.T.reshape(nz, 16)[:, 0]
+    _say(f"full slab z-only {prec}: oracle column done")
+    N = nx * ny * nz
+    u = np.zeros(3 * N)
+    u[:N] = np.repeat(ux_z, nx * ny)
+    ctx = _ctx(nx, ny, nz, True, prec, w.sigma, w.eta, w.tau, w.g)
+    ctx.init_thermal(np.repeat(n_z, nx * ny), u, np.repeat(T_z, nx * ny))
+    del u
+    ctx.step_thermal(3, 4)
+    Tg = ctx.read_temperature().reshape(nz, nx * ny)
+    assert np.all(Tg == Tg[:, :1]), "columns differ in T"
+    eT, edT = _rel(Tg[:, 0], To), _rel(Tg[:, 0] - T_z, To - T_z)
+    cols = np.random.default_rng(52).choice(nx * ny, 64, replace=False)
+    fg = ctx.read_populations().reshape(19, nz, nx * ny)[:, :, cols]
+    ctx.destroy()
+    assert np.all(fg == fg[:, :, :1]), "columns differ in f"
+    ef = _rel(fg[:, :, 0], fo)
+    _say(f"  f {ef:.2e}  T {eT:.2e}  change of T {edT:.2e}")
+    assert ef < tol_f and eT < tol_T and edT < tol_dT, (ef, eT, edT)
