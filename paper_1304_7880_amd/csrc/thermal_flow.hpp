@@ -115,108 +115,178 @@ __device__ __forceinline__ void th_vel(const Geom &g, const Pad &p, const V4<R> 
     u[2] = (jz[q] + R(0.5) * F[2 * N + q]) / r;
 }
 
+// The two energy kernels march along z: a thread owns the column (x, y) of a
+// 64 x 4 tile over zc planes (blockIdx.z: the chunk of planes), carrying
+// the fields of the planes z - 1, z, z + 1 of its own column in registers,
+// so that each plane of an array is read from memory about once; the x and
+// y neighbours come from the same plane, through the caches.
+__host__ __device__ constexpr int ENERGY_TX = 64, ENERGY_TY = 4;
+
+// the column's plane zz, or false beyond a wall (periodic: wrapped)
+__device__ __forceinline__ bool energy_plane(const Geom &g, int zz, int &zw)
+{
+    if (g.walls) {
+        zw = zz;
+        return zz >= 0 && zz < g.nz;
+    }
+    zw = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
+    return true;
+}
+
 // the part of dT/dt held fixed over the step's sub-steps:
 //   -u.grad T + (2/(3n)) (-div delta q - P:grad u + Q)
 // central differences (beyond a wall u is mirrored to -u, T to T), delta q =
 // B/(2 omega0) through the faces (none through a wall); P of eqs. pexplicit
 // and extrapressure with the step's A (stored xx, yy, zz, xy, xz, yz)
 template <typename R>
-__global__ __launch_bounds__(256) void k_energy_fixed(Geom g, Pad p, const V4<R> *__restrict__ ru1_p,
+__global__ __launch_bounds__(256) void k_energy_fixed(Geom g, Pad p, int zc, const V4<R> *__restrict__ ru1_p,
                                                       const R *__restrict__ T_p, const R *__restrict__ jx,
                                                       const R *__restrict__ jy, const R *__restrict__ jz,
                                                       const R *__restrict__ F, const R *__restrict__ A,
                                                       const R *__restrict__ Q, const R *__restrict__ B, R omega0,
                                                       R *__restrict__ Rfix)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
+    const int x = blockIdx.x * ENERGY_TX + (threadIdx.x & (ENERGY_TX - 1));
+    const int y = blockIdx.y * ENERGY_TY + (threadIdx.x / ENERGY_TX);
+    if (x >= g.nx || y >= g.ny) return;
+    const int z0 = blockIdx.z * zc, z1 = min(z0 + zc, g.nz);
     const long long N = g.N;
-    const int gb = pidx(p, x, y, z);
-    const R n = ru1_p[gb].x, Tr = T_p[gb];
-    R u0[3];
-    th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, y, z, u0);
-    R gu[3][3], gT[3], divdq = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int dx = a == 0, dy = a == 1, dz = a == 2;
-        int xp = x + dx, yp = y + dy, zp = z + dz, xm = x - dx, ym = y - dy, zm = z - dz;
-        xp = xp == g.nx ? 0 : xp;
-        xm = xm < 0 ? g.nx - 1 : xm;
-        yp = yp == g.ny ? 0 : yp;
-        ym = ym < 0 ? g.ny - 1 : ym;
-        bool okp = true, okm = true;
-        if (g.walls) {
-            okp = zp < g.nz;
-            okm = zm >= 0;
-        } else {
-            zp = zp == g.nz ? 0 : zp;
-            zm = zm < 0 ? g.nz - 1 : zm;
-        }
-        R up[3], um[3];
-        if (okp) th_vel<R>(g, p, ru1_p, jx, jy, jz, F, xp, yp, zp, up);
-        else up[0] = -u0[0], up[1] = -u0[1], up[2] = -u0[2];
-        if (okm) th_vel<R>(g, p, ru1_p, jx, jy, jz, F, xm, ym, zm, um);
-        else um[0] = -u0[0], um[1] = -u0[1], um[2] = -u0[2];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) gu[a][b] = R(0.5) * (up[b] - um[b]);
-        const R Tp = okp ? T_p[pidx(p, xp, yp, zp)] : Tr, Tm = okm ? T_p[pidx(p, xm, ym, zm)] : Tr;
-        gT[a] = R(0.5) * (Tp - Tm);
-        const long long ip = ((long long)zp * g.ny + yp) * g.nx + xp, im = ((long long)zm * g.ny + ym) * g.nx + xm;
-        const R q0 = B[a * N + i] / (R(2) * omega0);
-        const R fp = okp ? R(0.5) * (q0 + B[a * N + ip] / (R(2) * omega0)) : R(0);
-        const R fm = okm ? R(0.5) * (B[a * N + im] / (R(2) * omega0) + q0) : R(0);
-        divdq += fp - fm;
+    const int xp = x + 1 == g.nx ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+    const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+    auto node = [&](int zz) { return ((long long)zz * g.ny + y) * g.nx + x; };
+    const R h2w = R(2) * omega0;
+    // the column's planes z - 1 (m), z (0), z + 1 (p): u, T, B_z
+    R um[3] = {0, 0, 0}, u0[3], up[3] = {0, 0, 0}, Tm = 0, T0, Tp = 0, Bm = 0, B0, Bp = 0;
+    int zw;
+    bool hm = energy_plane(g, z0 - 1, zw);
+    if (hm) {
+        th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, y, zw, um);
+        Tm = T_p[pidx(p, x, y, zw)];
+        Bm = B[2 * N + node(zw)];
     }
-    // A0 (row-major) from the stored xx, yy, zz, xy, xz, yz
-    const R A0[3][3] = {{A[i], A[3 * N + i], A[4 * N + i]},
-                        {A[3 * N + i], A[N + i], A[5 * N + i]},
-                        {A[4 * N + i], A[5 * N + i], A[2 * N + i]}};
-    const R divu = gu[0][0] + gu[1][1] + gu[2][2];
-    R work = 0, adv = 0;
+    th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, y, z0, u0);
+    T0 = T_p[pidx(p, x, y, z0)];
+    B0 = B[2 * N + node(z0)];
+    for (int z = z0; z < z1; ++z) {
+        const bool hp = energy_plane(g, z + 1, zw);
+        if (hp) {
+            th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, y, zw, up);
+            Tp = T_p[pidx(p, x, y, zw)];
+            Bp = B[2 * N + node(zw)];
+        }
+        const long long i = node(z);
+        const R n = ru1_p[pidx(p, x, y, z)].x, Tr = T0;
+        R gu[3][3], gT[3], divdq = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        adv += u0[a] * gT[a];
+        for (int a = 0; a < 3; ++a) {
+            R vp[3], vm[3], Tpa, Tma, Bpa = 0, Bma = 0;
+            bool okp = true, okm = true;
+            if (a == 0) {
+                th_vel<R>(g, p, ru1_p, jx, jy, jz, F, xp, y, z, vp);
+                th_vel<R>(g, p, ru1_p, jx, jy, jz, F, xm, y, z, vm);
+                Tpa = T_p[pidx(p, xp, y, z)];
+                Tma = T_p[pidx(p, xm, y, z)];
+                Bpa = B[((long long)z * g.ny + y) * g.nx + xp];
+                Bma = B[((long long)z * g.ny + y) * g.nx + xm];
+            } else if (a == 1) {
+                th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, yp, z, vp);
+                th_vel<R>(g, p, ru1_p, jx, jy, jz, F, x, ym, z, vm);
+                Tpa = T_p[pidx(p, x, yp, z)];
+                Tma = T_p[pidx(p, x, ym, z)];
+                Bpa = B[N + ((long long)z * g.ny + yp) * g.nx + x];
+                Bma = B[N + ((long long)z * g.ny + ym) * g.nx + x];
+            } else {
+                okp = hp;
+                okm = hm;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    vp[b] = okp ? up[b] : -u0[b];
+                    vm[b] = okm ? um[b] : -u0[b];
+                }
+                Tpa = okp ? Tp : Tr;
+                Tma = okm ? Tm : Tr;
+                Bpa = Bp;
+                Bma = Bm;
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gu[a][b] = R(0.5) * (vp[b] - vm[b]);
+            gT[a] = R(0.5) * (Tpa - Tma);
+            const R q0 = (a == 2 ? B0 : B[a * N + i]) / h2w;
+            const R fp = okp ? R(0.5) * (q0 + Bpa / h2w) : R(0);
+            const R fm = okm ? R(0.5) * (Bma / h2w + q0) : R(0);
+            divdq += fp - fm;
+        }
+        // A0 (row-major) from the stored xx, yy, zz, xy, xz, yz
+        const R A0[3][3] = {{A[i], A[3 * N + i], A[4 * N + i]},
+                            {A[3 * N + i], A[N + i], A[5 * N + i]},
+                            {A[4 * N + i], A[5 * N + i], A[2 * N + i]}};
+        const R divu = gu[0][0] + gu[1][1] + gu[2][2];
+        R work = 0, adv = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            adv += u0[a] * gT[a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const R P = (a == b ? n * Tr : R(0)) -
+                            n * Tr / omega0 * (gu[a][b] + gu[b][a] - (a == b ? R(2) / R(3) * divu : R(0))) +
+                            R(2) / omega0 * A0[a][b];
+                work += P * gu[a][b];
+            }
+        }
+        Rfix[i] = -adv + R(2) / (R(3) * n) * (-divdq - work + Q[i]);
+        // advance the column: plane z becomes z - 1, z + 1 becomes z
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const R P = (a == b ? n * Tr : R(0)) -
-                        n * Tr / omega0 * (gu[a][b] + gu[b][a] - (a == b ? R(2) / R(3) * divu : R(0))) +
-                        R(2) / omega0 * A0[a][b];
-            work += P * gu[a][b];
+            um[b] = u0[b];
+            u0[b] = up[b];
         }
+        Tm = T0;
+        T0 = Tp;
+        Bm = B0;
+        B0 = Bp;
+        hm = true;
     }
-    Rfix[i] = -adv + R(2) / (R(3) * n) * (-divdq - work + Q[i]);
 }
 
 // one sub-step: T_out = T + (Rfix + (2/(3n)) (-div q_kin)) / nsub, the
-// kinetic flux through the six faces (none through a wall)
+// kinetic flux through the six faces (none through a wall); the column's
+// T and n of the planes z - 1, z, z + 1 carried (padded arrays: the plane
+// beyond a wall is there, zero, and not used)
 template <typename R>
-__global__ __launch_bounds__(256) void k_energy_sub(Geom g, Pad p, const R *__restrict__ T_p,
+__global__ __launch_bounds__(256) void k_energy_sub(Geom g, Pad p, int zc, const R *__restrict__ T_p,
                                                     const V4<R> *__restrict__ ru1_p, const R *__restrict__ Rfix,
                                                     R omega0, int nsub, R *__restrict__ T_out)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int x, y, z;
-    if (!node_of(g, i, x, y, z)) return;
-    const int gb = pidx(p, x, y, z);
-    const R n = ru1_p[gb].x, Tr = T_p[gb];
-    const int dp[3] = {1, p.PX, p.PXY};
-    R div = 0;
+    const int x = blockIdx.x * ENERGY_TX + (threadIdx.x & (ENERGY_TX - 1));
+    const int y = blockIdx.y * ENERGY_TY + (threadIdx.x / ENERGY_TX);
+    if (x >= g.nx || y >= g.ny) return;
+    const int z0 = blockIdx.z * zc, z1 = min(z0 + zc, g.nz);
+    int gb = pidx(p, x, y, z0);
+    R Tm = T_p[gb - p.PXY], nm = ru1_p[gb - p.PXY].x, T0 = T_p[gb], n0 = ru1_p[gb].x;
+    const R ck = -R(2.5) / omega0 * R(0.5);
+    for (int z = z0; z < z1; ++z, gb += p.PXY) {
+        const R Tp = T_p[gb + p.PXY], np_ = ru1_p[gb + p.PXY].x;
+        const R n = n0, Tr = T0;
+        R div = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R fp = 0, fm = 0;
-        const bool okp = !(a == 2 && g.walls && z == g.nz - 1), okm = !(a == 2 && g.walls && z == 0);
-        if (okp) {
-            const R Tp = T_p[gb + dp[a]], np_ = ru1_p[gb + dp[a]].x;
-            fp = -R(2.5) / omega0 * R(0.5) * (n * Tr + np_ * Tp) * (Tp - Tr);
+        for (int a = 0; a < 3; ++a) {
+            R fp = 0, fm = 0;
+            const bool okp = !(a == 2 && g.walls && z == g.nz - 1), okm = !(a == 2 && g.walls && z == 0);
+            R Tpa, npa, Tma, nma;
+            if (a == 2) {
+                Tpa = Tp, npa = np_, Tma = Tm, nma = nm;
+            } else {
+                const int d = a == 0 ? 1 : p.PX;
+                Tpa = T_p[gb + d], npa = ru1_p[gb + d].x, Tma = T_p[gb - d], nma = ru1_p[gb - d].x;
+            }
+            if (okp) fp = ck * (n * Tr + npa * Tpa) * (Tpa - Tr);
+            if (okm) fm = ck * (nma * Tma + n * Tr) * (Tr - Tma);
+            div += fp - fm;
         }
-        if (okm) {
-            const R Tm = T_p[gb - dp[a]], nm = ru1_p[gb - dp[a]].x;
-            fm = -R(2.5) / omega0 * R(0.5) * (nm * Tm + n * Tr) * (Tr - Tm);
-        }
-        div += fp - fm;
+        const long long i = ((long long)z * g.ny + y) * g.nx + x;
+        T_out[i] = Tr + (Rfix[i] + R(2) / (R(3) * n) * (-div)) / R(nsub);
+        Tm = T0, nm = n0, T0 = Tp, n0 = np_;
     }
-    T_out[i] = Tr + (Rfix[i] + R(2) / (R(3) * n) * (-div)) / R(nsub);
 }
 
 // after the collision: the stored post-collision populations gain the

@@ -991,7 +991,8 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
 //   k_thermal     Q, B, F^T at (rho, u1, T) into the next parity's h array
 //                 (rewritten by the collision only after they are read);
 //   k_th_force    F = rho (g + theta F^mf + sqrt(theta) F^v + F^T), A <- theta A;
-//   k_energy_fixed  the advection, work, delta q and Q part of dT/dt (rho_rd);
+//   k_energy_fixed  the advection, work, delta q and Q part of dT/dt (rho_rd),
+//                 marching along z like k_energy_sub;
 //   k_collide, then k_th_post  the temperature term relaxed at 1/tau;
 //   nsub sub-steps of k_energy_sub (u_rd between them, the last into T).
 template <typename R, typename D>
@@ -1037,9 +1038,13 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
     hipLaunchKernelGGL((k_th_force<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T,
                        kT, (const V4<R> *)c->fmf, (const R *)FT, R(p.g[0]), R(p.g[1]), R(p.g[2]), (R *)c->F,
                        (R *)c->A);
-    hipLaunchKernelGGL((k_energy_fixed<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p,
-                       (const R *)c->rho_p, (const R *)c->jx, (const R *)c->jy, (const R *)c->jz, (const R *)c->F,
-                       (const R *)c->A, (const R *)Qf, (const R *)Bf, omega0, Rfix);
+    // the energy kernels march along z in chunks of zc planes (a quarter of
+    // the lattice's, at most 4, or 16 on lattices of 2^21 nodes and more)
+    const int zc = std::max(1, std::min(g.nz / 4, g.N >= (1LL << 21) ? 16 : 4));
+    const dim3 egrid((g.nx + ENERGY_TX - 1) / ENERGY_TX, (g.ny + ENERGY_TY - 1) / ENERGY_TY, (g.nz + zc - 1) / zc);
+    hipLaunchKernelGGL((k_energy_fixed<R>), egrid, dim3(ENERGY_TX * ENERGY_TY), 0, c->stream, g, pd, zc,
+                       (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->jx, (const R *)c->jy,
+                       (const R *)c->jz, (const R *)c->F, (const R *)c->A, (const R *)Qf, (const R *)Bf, omega0, Rfix);
     HIPCHK(c, hipGetLastError());
     st = launch(c, K_COLLIDE, [&] {
         hipLaunchKernelGGL((k_collide<R, R, D, false>), gridt, dim3(bs), 0, c->stream, g, nt, (const R *)c->F,
@@ -1051,8 +1056,9 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
                        D(KT), D(1.0 / p.tau), (R *)c->h[nxt]);
     for (int s = 0; s < nsub; ++s) {
         const bool last = s == nsub - 1;
-        hipLaunchKernelGGL((k_energy_sub<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)c->rho_p,
-                           (const V4<R> *)c->ru1_p, (const R *)Rfix, omega0, nsub, last ? T : Tmid);
+        hipLaunchKernelGGL((k_energy_sub<R>), egrid, dim3(ENERGY_TX * ENERGY_TY), 0, c->stream, g, pd, zc,
+                           (const R *)c->rho_p, (const V4<R> *)c->ru1_p, (const R *)Rfix, omega0, nsub,
+                           last ? T : Tmid);
         if (!last)
             hipLaunchKernelGGL((k_pad<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)Tmid, (R *)c->rho_p);
     }
