@@ -729,10 +729,12 @@ static void energy_update(const wdlb_ref_cfg *c, const double *rho, const double
 }
 
 /* nsteps steps of the coupled thermal flow in place on f and T:
- *   fields as in O1-O4 with theta = T / kT: F^mf scaled by theta (and u1
- *   with it), F^v by sqrt(theta), A by theta (Sec. 3: the mean-field force
- *   carries k_B T, the viscous force sqrt(k_B T), A_ij k_B T), plus the
- *   thermal force F^T (eq. thermalforce) with u1;
+ *   fields as in O1-O4 with theta = T / kT: F^mf scaled by theta, F^v by
+ *   sqrt(theta), A by theta (Sec. 3: the mean-field force carries k_B T,
+ *   the viscous force sqrt(k_B T), A_ij k_B T), plus the thermal force F^T
+ *   (eq. thermalforce, from n and T alone); u1 = j/rho + (g + theta F^mf +
+ *   F^T)/2 carries every force known before the viscous sums, and F^v, A
+ *   and Q are formed with it;
  *   O5 with the temperature term of the equilibrium (theta_term, relaxed
  *   at 1/tau; the forcing and A-source as in the isothermal step);
  *   O6 stream; then the energy balance (energy_update) with the step's u,
@@ -765,10 +767,18 @@ int wdlb_ref_step_thermal(const wdlb_ref_cfg *c, double *f, double *T, int64_t n
             if (rc == REF_OK) rc = wdlb_ref_meanfield(c, rho, nb, fmf);
             if (rc != REF_OK) break;
         }
+        /* F^T depends on n and T alone (eq. thermalforce): formed first (the
+         * velocity argument only enters Q), so that u1 carries every force
+         * known before the viscous sums, F^T with the others */
+        if (c->nonlocal) {
+            for (long i = 0; i < 3 * N; ++i) u1[i] = 0.0;
+            rc = wdlb_ref_thermal(c, rho, nb, u1, T, Q, B, FT);
+            if (rc != REF_OK) break;
+        }
         for (long i = 0; i < N; ++i)
             for (int d = 0; d < 3; ++d)
-                u1[(long)d * N + i] =
-                    j[(long)d * N + i] / rho[i] + 0.5 * (c->g[d] + T[i] / KT * fmf[(long)d * N + i]);
+                u1[(long)d * N + i] = j[(long)d * N + i] / rho[i] +
+                                      0.5 * (c->g[d] + T[i] / KT * fmf[(long)d * N + i] + FT[(long)d * N + i]);
         if (c->nonlocal) {
             rc = wdlb_ref_viscous(c, rho, nb, u1, fv, A);
             if (rc == REF_OK) rc = wdlb_ref_thermal(c, rho, nb, u1, T, Q, B, FT);

@@ -21,14 +21,20 @@ mathematics fix:
   dn/n) runs at the adiabatic speed of the Carnahan-Starling fluid,
   c^2 = kT d(n Z)/dn + (2/3) T Z^2 (p = n T Z; the energy balance with the
   work -p div u of the kinetic pressure and of Q's compression term), within
-  1 % at sigma = 8 -- not at the isothermal kT d(nZ)/dn, 48 % lower.
+  1 % at sigma = 8 -- not at the isothermal kT d(nZ)/dn, 48 % lower;
+- the heat mode: a temperature wave at constant pressure (dn/n = -(Z / d(nZ)/dn)
+  dT/T) decays at lambda q^2 / (n c_p), c_p = c_v gamma with gamma = c_ad^2 /
+  c_T^2 -- the rate of the same wave in the fluid at rest (oracle/conduction.py,
+  Sec. 4's conductivity) divided by gamma, within 2 % at sigma = 8.  It needs
+  u1 to carry F^T/2: with u1 short of it, Q's compression term sees the
+  divergence of F^T (a Laplacian of T) and the rate falls 10 % short.
 """
 import math
 
 import numpy as np
 import pytest
 
-from oracle import ref
+from oracle import conduction, ref
 from paper_1304_7880_amd.transport import carnahan_starling_c2, fit_damped_cosine
 from paper_1304_7880_amd.workloads import packing_to_density, random_fields, random_temperature
 
@@ -146,3 +152,29 @@ def test_rest_in_a_layered_density_keeps_the_temperature(walls):
             assert dT < 1e-12 * T1, dT
         else:
             assert dT > 1e-8 * T1, dT      # the test sees a wrong velocity
+
+
+def test_heat_mode_decays_at_lambda_over_n_cp():
+    sigma, eta, tau, L, eps = 8.0, 0.25, 1.0, 128, 1e-3
+    cfg = ref.Config(4, 4, L, False, sigma, tau)
+    N = cfg.N
+    n0 = packing_to_density(eta, sigma)
+    Z = (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+    dnZ = carnahan_starling_c2(eta) / KT
+    s = np.sin(2 * math.pi * np.arange(L) / L)
+    st = ref.ThermalState.from_fields(cfg, np.repeat(n0 * (1 - Z / dnZ * eps * s), 16), np.zeros(3 * N),
+                                      np.repeat(KT * (1 + eps * s), 16))
+    sr = np.repeat(s, 16)
+    r = conduction.rate(cfg, np.full(N, n0), KT * (1 + eps * sr), 1.0 / tau)
+    r_rest = -float(r @ sr) / float(sr @ sr) / (KT * eps)
+    gamma = (carnahan_starling_c2(eta) + 2.0 / 3.0 * KT * Z * Z) / carnahan_starling_c2(eta)
+    ts, amps = [], []
+    for t in range(0, 601, 5):
+        ts.append(t)
+        amps.append(float((st.T.reshape(L, 16).mean(1) - KT) @ s))
+        st.step(5, 4)
+    ts, amps = np.array(ts, dtype=np.float64), np.array(amps)
+    sel = ts >= 100
+    rate = -np.polyfit(ts[sel], np.log(amps[sel]), 1)[0]
+    assert abs(rate / (r_rest / gamma) - 1) < 0.02, (rate, r_rest / gamma)
+    assert abs(rate / r_rest - 1) > 0.4          # not the rate at constant density
