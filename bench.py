@@ -408,7 +408,9 @@ def thermal_flow_bench(w, prec, steps=3, warmup=1, nsub=4):
     ms = e0.elapsed_time(e1) / steps
     ctx.profile(True)
     ctx.step_thermal(steps, nsub)
-    kst = {k: v[0] / v[1] for k, v in ctx.profile_read().items() if v[1]}
+    prof = {k: v for k, v in ctx.profile_read().items() if v[1]}
+    kst = {k: v[0] / steps for k, v in prof.items()}          # ms per step
+    kavg = {k: v[0] / v[1] for k, v in prof.items()}          # ms per launch
     ctx.profile(False)
     tile, spec = ctx.get_tile()
     Tn = ctx.read_temperature()
@@ -423,8 +425,8 @@ def thermal_flow_bench(w, prec, steps=3, warmup=1, nsub=4):
            "other_kernels_ms_per_step": round(ms - sum(kst.values()), 3),
            "T_range": [float(Tn.min()), float(Tn.max())]}
     for k, ops in (("k_shell", SHELL_OPS_PER_OFFSET), ("k_thermal", THERMAL_OPS_PER_OFFSET)):
-        if k in kst:
-            a = ops * nS * w.N / (kst[k] * 1e-3) / 1e12
+        if k in kavg:
+            a = ops * nS * w.N / (kavg[k] * 1e-3) / 1e12
             out[f"roofline_{k}"] = {"kernel": names[k], "bound": "alu", "achieved": round(a, 3), "peak": peak,
                                     "unit": "TFLOP/s", "frac": round(a / peak, 4),
                                     "count": f"{ops:g} operations per shell offset x {nS} offsets x {w.N} nodes"}

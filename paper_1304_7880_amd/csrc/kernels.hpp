@@ -1040,18 +1040,20 @@ __device__ __forceinline__ void mf_finish(const Geom &g, const Pad &p, int x, in
 template <typename R>
 __device__ __forceinline__ void sh_finish_v(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
                                             R gx, R gy, R gz, int smdb, const V4<R> &fm, R *__restrict__ Fo,
-                                            R *__restrict__ Ao);
+                                            R *__restrict__ Ao, R *__restrict__ So);
 template <typename R>
 __device__ __forceinline__ void sh_finish(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
                                           R gx, R gy, R gz, int smdb, const V4<R> *__restrict__ fmf,
-                                          R *__restrict__ Fo, R *__restrict__ Ao)
+                                          R *__restrict__ Fo, R *__restrict__ Ao, R *__restrict__ So)
 {
-    sh_finish_v<R>(g, x, y, z, r0, acc, cv, cA, gx, gy, gz, smdb, fmf[(z * g.ny + y) * g.nx + x], Fo, Ao);
+    sh_finish_v<R>(g, x, y, z, r0, acc, cv, cA, gx, gy, gz, smdb, fmf[(z * g.ny + y) * g.nx + x], Fo, Ao, So);
 }
+// So (optional, null in the isothermal step): the trace sum sum_e k.W of the
+// shell, from which the coupled thermal flow forms the compression term of Q
 template <typename R>
 __device__ __forceinline__ void sh_finish_v(const Geom &g, int x, int y, int z, R r0, const R (&acc)[9], R cv, R cA,
                                             R gx, R gy, R gz, int smdb, const V4<R> &fm, R *__restrict__ Fo,
-                                            R *__restrict__ Ao)
+                                            R *__restrict__ Ao, R *__restrict__ So)
 {
     const long long N = g.N;
     const int i = (z * g.ny + y) * g.nx + x;
@@ -1079,6 +1081,7 @@ __device__ __forceinline__ void sh_finish_v(const Geom &g, int x, int y, int z, 
     Ao[3 * N + i] = Axy;
     Ao[4 * N + i] = Axz;
     Ao[5 * N + i] = Ayz;
+    if (So) So[i] = acc[3] + acc[4] + acc[5];
 }
 
 // gamma of the four mirror images of quad (a, b, c) for the generic kernels:
@@ -1164,7 +1167,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
                                                       const Quad<R> *__restrict__ quads,
                                                       const int *__restrict__ qstart, R cv, R cA, R gx, R gy, R gz,
                                                       int smdb, int tiles_x, int tiles_y, int tiles_z,
-                                                      R *__restrict__ Fo, R *__restrict__ Ao)
+                                                      R *__restrict__ Fo, R *__restrict__ Ao, R *__restrict__ So)
 {
     constexpr bool GL = NG > 0;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1202,7 +1205,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell(Geom g, Pad p, int Rr, con
         if (c + 1 <= Rr) cstep(std::integral_constant<int, 1>{}, c + 1);
     }
     if (!valid) return;
-    sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao);
+    sh_finish<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fmf, Fo, Ao, So);
 }
 
 // ---------------------------------------------------------------------------
@@ -1353,7 +1356,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
                                                         const R *__restrict__ gam_p, const V4<R> *__restrict__ fmf,
                                                         R cv, R cA, R gx, R gy, R gz, int smdb, int tiles_x,
                                                         int tiles_y, int tiles_z, R *__restrict__ Fo,
-                                                        R *__restrict__ Ao)
+                                                        R *__restrict__ Ao, R *__restrict__ So)
 {
     constexpr bool GL = NG > 0;
     using SH = Shell<S2>;
@@ -1456,7 +1459,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_shell_s(Geom g, Pad p, const V4<
         rg.template end<S>(c);
     });
     if (!valid) return;
-    sh_finish_v<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fm, Fo, Ao);
+    sh_finish_v<R>(g, x, y, z, c0.x, acc, cv, cA, gx, gy, gz, smdb, fm, Fo, Ao, So);
 }
 #undef WDLB_GAM
 

@@ -4,9 +4,10 @@
 // R is the storage real (FP64 or FP32); the viscous force is recovered from
 // the step's total force, to the rounding of that total.
 //
-// With theta = T / kT at every node: the mean-field force and u1 carry
-// theta, the viscous force sqrt(theta), A theta (Sec. 3: F^mf ~ k_B T,
-// F^v ~ sqrt(k_B T), A_ij ~ k_B T), the thermal force F^T is added, the
+// With theta = T / kT at every node: the mean-field force carries theta,
+// the viscous force sqrt(theta), A theta (Sec. 3: F^mf ~ k_B T,
+// F^v ~ sqrt(k_B T), A_ij ~ k_B T), the thermal force F^T is added (and u1
+// of the viscous and thermal sums carries it with the other forces), the
 // populations relax towards the equilibrium with its temperature term
 // w_a rho (3/2)(theta - 1)(|c_a|^2 - 1), and T follows the energy balance
 // with flow (Sec. 2 eq. energyequation; the heat flux of eq. qexplicit, the
@@ -54,13 +55,15 @@ __global__ __launch_bounds__(256) void k_th_init(Geom g, const V4<R> *__restrict
     }
 }
 
-// after the mean-field kernel: F^mf <- theta F^mf and u1 = j/rho + (g + theta F^mf)/2
-// into the padded (rho, u1) array with its images; a temperature that is not
-// positive and finite raises FLAG_T
+// after the mean-field and the first thermal kernel: F^mf <- theta F^mf and
+// u1 = j/rho + (g + theta F^mf + F^T)/2 (every force known before the
+// viscous sums) into the padded (rho, u1) array with its images; a
+// temperature that is not positive and finite raises FLAG_T
 template <typename R>
 __global__ __launch_bounds__(256) void k_th_u1(Geom g, Pad p, const R *__restrict__ T, R kT, const R *__restrict__ jx,
-                                               const R *__restrict__ jy, const R *__restrict__ jz, R gx, R gy, R gz,
-                                               V4<R> *__restrict__ fmf, V4<R> *__restrict__ ru1_p, int *flag)
+                                               const R *__restrict__ jy, const R *__restrict__ jz,
+                                               const R *__restrict__ FT, R gx, R gy, R gz, V4<R> *__restrict__ fmf,
+                                               V4<R> *__restrict__ ru1_p, int *flag)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
@@ -73,24 +76,38 @@ __global__ __launch_bounds__(256) void k_th_u1(Geom g, Pad p, const R *__restric
     f.y = th * f.y;
     f.z = th * f.z;
     fmf[i] = f;
-    const V4<R> v = {rr, jx[i] / rr + R(0.5) * (gx + f.x), jy[i] / rr + R(0.5) * (gy + f.y),
-                     jz[i] / rr + R(0.5) * (gz + f.z)};
+    const long long N = g.N;
+    const V4<R> v = {rr, jx[i] / rr + R(0.5) * (gx + f.x + FT[i]), jy[i] / rr + R(0.5) * (gy + f.y + FT[N + i]),
+                     jz[i] / rr + R(0.5) * (gz + f.z + FT[2 * N + i])};
     for_images(g, p, x, y, z, [&](int k) { ru1_p[k] = v; });
 }
 
-// after the viscous/SMDB kernel (whose F holds rho (g + theta F^mf + F^v(kT))):
-// F = rho (g + theta F^mf + sqrt(theta) F^v(kT) + F^T) and A <- theta A
+// the velocity of every entry of the padded (rho, u1) array set to zero
+// (images and padding included), for the thermal fields at u = 0
+template <typename R>
+__global__ __launch_bounds__(256) void k_ru_rest(long long NP, V4<R> *__restrict__ ru_p)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NP) return;
+    ru_p[k] = V4<R>{ru_p[k].x, R(0), R(0), R(0)};
+}
+
+// after the viscous/SMDB kernel (whose F holds rho (g + theta F^mf + F^v(kT))
+// and whose trace sums S = sum_e k.W are in S):
+// F = rho (g + theta F^mf + sqrt(theta) F^v(kT) + F^T), A <- theta A, and Q
+// (its conduction part from the thermal kernel at u = 0) gains its
+// compression part -(n sigma^2 T / 2) S (eq. campob1)
 template <typename R>
 __global__ __launch_bounds__(256) void k_th_force(Geom g, Pad p, const V4<R> *__restrict__ ru1_p,
                                                   const R *__restrict__ T, R kT, const V4<R> *__restrict__ fmf,
-                                                  const R *__restrict__ FT, R gx, R gy, R gz, R *__restrict__ F,
-                                                  R *__restrict__ A)
+                                                  const R *__restrict__ FT, const R *__restrict__ S, R s2, R gx, R gy,
+                                                  R gz, R *__restrict__ F, R *__restrict__ A, R *__restrict__ Q)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
     if (!node_of(g, i, x, y, z)) return;
     const long long N = g.N;
-    const R r = ru1_p[pidx(p, x, y, z)].x, th = T[i] / kT, sq = sqrt(th);
+    const R r = ru1_p[pidx(p, x, y, z)].x, Ti = T[i], th = Ti / kT, sq = sqrt(th);
     const V4<R> fm = fmf[i];
     const R gg[3] = {gx, gy, gz}, fmc[3] = {fm.x, fm.y, fm.z};
 #pragma unroll
@@ -100,6 +117,7 @@ __global__ __launch_bounds__(256) void k_th_force(Geom g, Pad p, const V4<R> *__
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) A[k * N + i] = th * A[k * N + i];
+    Q[i] += r * s2 * (R(-0.5) * Ti * S[i]);
 }
 
 // velocity u = (j + F/2)/rho of node (x, y, z) (unpadded index q, padded density)

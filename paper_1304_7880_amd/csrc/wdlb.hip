@@ -75,6 +75,7 @@ struct wdlb_ctx {
     bool inited;
     int static_dev = -1;  // device whose static workspace this context holds (wdlb_create_static), else -1
     int shell_part = 3;   // bit 0: launch the mean-field kernel, bit 1: the viscous/SMDB kernel (the thermal step runs them apart)
+    void *shell_trace = nullptr;  // the viscous/SMDB kernel's trace sums go here when set (the thermal step)
     std::string err;
     // event timing of the step kernels
     int prof = 0;  // bit k: time kernel k
@@ -506,7 +507,8 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
         hipLaunchKernelGGL(ksh, grid, block, lsh, c->stream, g, c->pad, c->reach, (const V4<R> *)c->ru1_p,
                            (const R *)c->gam_p, (const V4<R> *)c->fmf, (const Quad<R> *)c->quads,
                            (const int *)c->qstart, R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s),
-                           R(p.g[0]), R(p.g[1]), R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A);
+                           R(p.g[0]), R(p.g[1]), R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A,
+                           (R *)c->shell_trace);
     });
 }
 
@@ -550,7 +552,7 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
             hipLaunchKernelGGL(ksh, dim3(tx * ty * tz), dim3(T.TX * T.TY * T.TZ), lsh, c->stream, g, c->pad,
                                (const V4<R> *)c->ru1_p, (const R *)c->gam_p, (const V4<R> *)c->fmf,
                                R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]),
-                               R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A);
+                               R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A, (R *)c->shell_trace);
         });
     }
 }
@@ -985,12 +987,16 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
 // updated in place.  The step's kernels
 // with the mean-field and viscous/SMDB kernels launched apart:
 //   k_moments, k_density, k_meanfield;
-//   k_th_u1       F^mf <- theta F^mf, u1 with it (into the (rho, u1) array);
-//   k_shell       F^v and A from that u1;
+//   k_ru_rest     the velocity of the padded (rho, u1) array set to zero;
 //   k_pad         T over the density array (no longer needed);
-//   k_thermal     Q, B, F^T at (rho, u1, T) into the next parity's h array
-//                 (rewritten by the collision only after they are read);
-//   k_th_force    F = rho (g + theta F^mf + sqrt(theta) F^v + F^T), A <- theta A;
+//   k_thermal     F^T, B and the conduction part of Q (all three at u = 0:
+//                 they depend on n and T alone) into the next parity's h
+//                 array (rewritten by the collision only after they are read);
+//   k_th_u1       F^mf <- theta F^mf, u1 = j/rho + (g + theta F^mf + F^T)/2
+//                 (into the (rho, u1) array);
+//   k_shell       F^v and A from that u1, and the trace sums sum_e k.W;
+//   k_th_force    F = rho (g + theta F^mf + sqrt(theta) F^v + F^T), A <- theta A,
+//                 Q += its compression part -(n sigma^2 T / 2) sum_e k.W;
 //   k_energy_fixed  the advection, work, delta q and Q part of dT/dt (rho_rd),
 //                 marching along z like k_energy_sub;
 //   k_collide, then k_th_post  the temperature term relaxed at 1/tau;
@@ -1011,7 +1017,7 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
     const wdlb_params &p = c->prm;
     const R kT = R(KT), omega0 = R(1.0 / p.tau);
     const long long N = g.N;
-    R *Qf = (R *)c->h[nxt], *Bf = Qf + N, *FT = Qf + 4 * N;
+    R *Qf = (R *)c->h[nxt], *Bf = Qf + N, *FT = Qf + 4 * N, *Sk = Qf + 7 * N;
     R *Rfix = (R *)c->rho_rd, *Tmid = (R *)c->u_rd;
     wdlb_status st = launch(c, K_MOMENTS, [&] {
         hipLaunchKernelGGL((k_moments<R, R, D>), gridt, dim3(bs), 0, c->stream, g, nt, pd, ru_in, h_in, (R *)c->rho_p,
@@ -1021,23 +1027,30 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
     if ((st = launch_density<R>(c)) != WDLB_OK) return st;
     struct PartReset {
         wdlb_ctx *c;
-        ~PartReset() { c->shell_part = 3; }
+        ~PartReset()
+        {
+            c->shell_part = 3;
+            c->shell_trace = nullptr;
+        }
     } reset{c};
     c->shell_part = 1;
     if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
-    hipLaunchKernelGGL((k_th_u1<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, kT, (const R *)c->jx,
-                       (const R *)c->jy, (const R *)c->jz, R(p.g[0]), R(p.g[1]), R(p.g[2]), (V4<R> *)c->fmf,
-                       (V4<R> *)c->ru1_p, c->flag);
-    HIPCHK(c, hipGetLastError());
-    c->shell_part = 2;
-    if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
-    c->shell_part = 3;
+    hipLaunchKernelGGL((k_ru_rest<R>), grid1(pd.NP, bs), dim3(bs), 0, c->stream, pd.NP, (V4<R> *)c->ru1_p);
     hipLaunchKernelGGL((k_pad<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, (R *)c->rho_p);
     HIPCHK(c, hipGetLastError());
     if ((st = launch_thermal<R>(c, Qf, Bf, FT)) != WDLB_OK) return st;
+    hipLaunchKernelGGL((k_th_u1<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, kT, (const R *)c->jx,
+                       (const R *)c->jy, (const R *)c->jz, (const R *)FT, R(p.g[0]), R(p.g[1]), R(p.g[2]),
+                       (V4<R> *)c->fmf, (V4<R> *)c->ru1_p, c->flag);
+    HIPCHK(c, hipGetLastError());
+    c->shell_part = 2;
+    c->shell_trace = Sk;
+    if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
+    c->shell_part = 3;
+    c->shell_trace = nullptr;
     hipLaunchKernelGGL((k_th_force<R>), grid, dim3(bs), 0, c->stream, g, pd, (const V4<R> *)c->ru1_p, (const R *)T,
-                       kT, (const V4<R> *)c->fmf, (const R *)FT, R(p.g[0]), R(p.g[1]), R(p.g[2]), (R *)c->F,
-                       (R *)c->A);
+                       kT, (const V4<R> *)c->fmf, (const R *)FT, (const R *)Sk, R(p.sigma * p.sigma), R(p.g[0]),
+                       R(p.g[1]), R(p.g[2]), (R *)c->F, (R *)c->A, Qf);
     // the energy kernels march along z in chunks of zc planes (a quarter of
     // the lattice's, at most 4, or 16 on lattices of 2^21 nodes and more)
     const int zc = std::max(1, std::min(g.nz / 4, g.N >= (1LL << 21) ? 16 : 4));
