@@ -259,3 +259,34 @@ def test_full_slab_z_only_matches_the_column_oracle(prec, tol_f, tol_T, tol_dT):
     ef = _rel(fg[:, :, 0], fo)
     _say(f"  f {ef:.2e}  T {eT:.2e}  change of T {edT:.2e}")
     assert ef < tol_f and eT < tol_T and edT < tol_dT, (ef, eT, edT)
+
+
+def test_heat_mode_decays_at_lambda_over_n_cp():
+    """The oracle's heat-mode pin on the GPU path (FP64): a temperature wave at
+    constant pressure, sigma = 8, decays at the rate of the same wave at rest
+    (the conduction oracle) divided by gamma = c_ad^2 / c_T^2, within 2 %."""
+    from oracle import conduction
+    sigma, eta, tau, L, eps = 8.0, 0.25, 1.0, 128, 1e-3
+    N = 16 * L
+    cfg = ref.Config(4, 4, L, False, sigma, tau)
+    n0 = packing_to_density(eta, sigma)
+    Z = (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+    dnZ = carnahan_starling_c2(eta) / KT
+    s = np.sin(2 * math.pi * np.arange(L) / L)
+    sr = np.repeat(s, 16)
+    r = conduction.rate(cfg, np.full(N, n0), KT * (1 + eps * sr), 1.0 / tau)
+    r_rest = -float(r @ sr) / float(sr @ sr) / (KT * eps)
+    gamma = (carnahan_starling_c2(eta) + 2.0 / 3.0 * KT * Z * Z) / carnahan_starling_c2(eta)
+    ctx = _ctx(4, 4, L, False, "fp64", sigma, eta, tau)
+    ctx.init_thermal(np.repeat(n0 * (1 - Z / dnZ * eps * s), 16), np.zeros(3 * N), np.repeat(KT * (1 + eps * s), 16))
+    ts, amps = [], []
+    for t in range(0, 601, 5):
+        ts.append(t)
+        amps.append(float((ctx.read_temperature().reshape(L, 16).mean(1) - KT) @ s))
+        ctx.step_thermal(5, 4)
+    ctx.destroy()
+    ts, amps = np.array(ts, dtype=np.float64), np.array(amps)
+    sel = ts >= 100
+    rate = -np.polyfit(ts[sel], np.log(amps[sel]), 1)[0]
+    _say(f"  heat mode rate {rate:.6e}  lambda q^2/(n c_p) {r_rest / gamma:.6e}")
+    assert abs(rate / (r_rest / gamma) - 1) < 0.02
