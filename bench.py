@@ -617,6 +617,9 @@ def main():
                              "kernels_ms_per_step": {k: round(v, 5) for k, v in m["kernels_ms_per_step"].items()}}
         print(f"bench: thermal fields on {w.name}", file=sys.stderr, flush=True)
         out["thermal_fields"] = thermal_bench(w, args.precision)
+        tf_prec = args.precision if args.precision in ("fp64", "fp32", "fp32_local64") else "fp32_local64"
+        print(f"bench: coupled thermal flow on {w.name}, {tf_prec}", file=sys.stderr, flush=True)
+        out["thermal_flow"] = thermal_flow_bench(w, tf_prec, 5, 2)
     if args.serving:
         out["serving"] = serving_bench(args.serving, args.serving_planes, args.serving_max_steps,
                                        plain=not args.serving_no_plain)

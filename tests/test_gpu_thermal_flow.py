@@ -290,3 +290,27 @@ def test_heat_mode_decays_at_lambda_over_n_cp():
     rate = -np.polyfit(ts[sel], np.log(amps[sel]), 1)[0]
     _say(f"  heat mode rate {rate:.6e}  lambda q^2/(n c_p) {r_rest / gamma:.6e}")
     assert abs(rate / (r_rest / gamma) - 1) < 0.02
+
+
+def test_checkpoint_and_resume():
+    """Save the state (wdlb_save_state) and T after three coupled steps, load
+    both into a new context, step three more: the same populations and T as
+    six steps without the interruption, bit for bit."""
+    nx, ny, nz, sigma, eta, tau = 14, 12, 13, 4.0, 0.3, 0.9
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=61)
+    T0 = random_temperature(nx, ny, nz, KT, 0.05, seed=62)
+    a = _ctx(nx, ny, nz, True, "fp32_local64", sigma, eta, tau)
+    a.init_thermal(n, u, T0)
+    a.step_thermal(3, 4)
+    blob, Tk = a.save_state(), a.read_temperature()
+    a.step_thermal(3, 4)
+    fa, Ta = a.read_populations(), a.read_temperature()
+    a.destroy()
+    b = _ctx(nx, ny, nz, True, "fp32_local64", sigma, eta, tau)
+    b.init_thermal(n, u, T0)          # allocates b.T; the state and T are then replaced
+    b.load_state(blob)
+    b.T.copy_(__import__("torch").from_numpy(Tk.astype(np.float32)))
+    b.step_thermal(3, 4)
+    fb, Tb = b.read_populations(), b.read_temperature()
+    b.destroy()
+    assert np.array_equal(fa, fb) and np.array_equal(Ta, Tb)
