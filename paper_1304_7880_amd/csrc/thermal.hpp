@@ -97,13 +97,17 @@ __device__ __forceinline__ void th_finish(const Geom &g, int x, int y, int z, R 
     FTo[2 * N + i] = kf * az;
 }
 
+// NoU (all three thermal kernels): the fields at u = 0 -- the velocity is not
+// used and Q keeps its conduction part only (the coupled thermal flow forms
+// its compression part from the viscous kernel's trace sums).
+//
 // k_thermal: one lane per node on 32 x 8 tiles of a plane; the shell from
 // the quad table (mirror groups (+-a, +-b, c), in the table's order), the
 // images' rho, u, T and contact values read through the caches.  A state
 // that does not depend on x (or y) gives exactly zero x (y) components.  The
 // contact values of the density kernel carry the shell weight w_S;
 // s2 = sigma^2.  Used where the LDS rings of k_thermal_r do not fit.
-template <typename R>
+template <typename R, bool NoU = false>
 __global__ __launch_bounds__(256) void k_thermal(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
                                                  const R *__restrict__ T_p, const R *__restrict__ gam_p,
                                                  const Quad<R> *__restrict__ quads, int nq, R s2, int tiles_x,
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void k_thermal(Geom g, Pad p, const V4<R> *__r
         }
         th_quad<R>(Qd, gm, sm, tm, c0, T0, ax, ay, az, aT, aV);
     }
-    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, NoU ? R(0) : aV, Qo, Bo, FTo);
 }
 
 // k_thermal_r: the same sums on TX x TY x TZ tiles with (rho, u) and T
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void k_thermal(Geom g, Pad p, const V4<R> *__r
 // ShellRings), the contact values read through the caches.  The groups are
 // visited in the same order as by k_thermal, with the same arithmetic, so
 // the two kernels give the same bits.
-template <typename R, int TX, int TY, int TZ, int NR>
+template <typename R, int TX, int TY, int TZ, int NR, bool NoU = false>
 __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_r(Geom g, Pad p, int Rr, const V4<R> *__restrict__ ru_p,
                                                           const R *__restrict__ T_p, const R *__restrict__ gam_p,
                                                           const Quad<R> *__restrict__ quads,
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_r(Geom g, Pad p, int Rr,
         rg.template end<0>(c);   // stores the next (rho, u) plane, then the barrier
     }
     if (!valid) return;
-    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, NoU ? R(0) : aV, Qo, Bo, FTo);
 }
 
 // k_thermal_s: the same sums compiled for the shell of 2 sigma = S2 (FP32):
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_r(Geom g, Pad p, int Rr,
 // offset is a scalar (see gamma_img).  Groups with a or b zero sum their
 // distinct images once with doubled (quadrupled) weights, which is exact, so
 // the result is bit-identical to k_thermal_r and k_thermal.
-template <typename R, int S2, int TX, int TY, int TZ, int NR>
+template <typename R, int S2, int TX, int TY, int TZ, int NR, bool NoU = false>
 __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
                                                           const R *__restrict__ T_p, const R *__restrict__ gam_p,
                                                           R s2, int tiles_x, int tiles_y, int tiles_z,
@@ -349,12 +353,12 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V
         pin(ay);
         pin(az);
         pin(aT);
-        pin(aV);
+        if constexpr (!NoU) pin(aV);
         if constexpr (c < RC) tr.template store<0>(twin, (c + TZ + RC) % NS);
         rg.template end<0>(c);
     });
     if (!valid) return;
-    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, aV, Qo, Bo, FTo);
+    th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, NoU ? R(0) : aV, Qo, Bo, FTo);
 }
 
 // LDS bytes of k_thermal_r: the (rho, u) ring, then the T ring

@@ -82,16 +82,6 @@ __global__ __launch_bounds__(256) void k_th_u1(Geom g, Pad p, const R *__restric
     for_images(g, p, x, y, z, [&](int k) { ru1_p[k] = v; });
 }
 
-// the velocity of every entry of the padded (rho, u1) array set to zero
-// (images and padding included), for the thermal fields at u = 0
-template <typename R>
-__global__ __launch_bounds__(256) void k_ru_rest(long long NP, V4<R> *__restrict__ ru_p)
-{
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= NP) return;
-    ru_p[k] = V4<R>{ru_p[k].x, R(0), R(0), R(0)};
-}
-
 // after the viscous/SMDB kernel (whose F holds rho (g + theta F^mf + F^v(kT))
 // and whose trace sums S = sum_e k.W are in S):
 // F = rho (g + theta F^mf + sqrt(theta) F^v(kT) + F^T), A <- theta A, and Q

@@ -773,14 +773,14 @@ size_t state_bytes(const wdlb_ctx *c)
 // The thermal-field kernels: compiled for the shell (FP32, compiled sigma),
 // else table-driven on LDS-ring tiles (32 x 8 x 2 in FP32, 32 x 8 x 1 in
 // FP64) where the two rings fit, else the cache kernel.
-template <typename R, int TZ, int NR>
+template <typename R, int TZ, int NR, bool NoU>
 wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
     const Geom g = c->g;
     const double s = c->prm.sigma;
     const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8, tz = (g.nz + TZ - 1) / TZ;
     const size_t lds = thermal_lds_bytes(32, 8, TZ, c->reach, sizeof(R));
-    auto kern = k_thermal_r<R, 32, 8, TZ, NR>;
+    auto kern = k_thermal_r<R, 32, 8, TZ, NR, NoU>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(32 * 8 * TZ), lds, c->stream, g, c->pad,
@@ -791,7 +791,7 @@ wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 
 // compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
 // sigma = 10 their two rings (75 KB) leave room for two blocks per CU
-template <int S2>
+template <int S2, bool NoU>
 wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
 {
     constexpr int TX = 32, TY = 16, TZ = 1, NT = TX * TY * TZ;
@@ -802,7 +802,7 @@ wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
     const double s = c->prm.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
     const size_t lds = thermal_lds_bytes(TX, TY, TZ, RC, 4);
-    auto kern = k_thermal_s<float, S2, TX, TY, TZ, NR>;
+    auto kern = k_thermal_s<float, S2, TX, TY, TZ, NR, NoU>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
@@ -811,7 +811,7 @@ wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
     });
 }
 
-template <typename R>
+template <typename R, bool NoU = false>
 wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
     if constexpr (std::is_same<R, float>::value) {
@@ -820,11 +820,11 @@ wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
         // (wdlb_set_tile >= 0) selects the table-driven kernels here too
         if (c->tile_req < 0 && 4.0 * (double)c->pad.NP < 2.0e9) {
             switch (specialised_s2(c->prm.sigma)) {
-            case 6: return launch_thermal_s<6>(c, Q, B, FT);
-            case 8: return launch_thermal_s<8>(c, Q, B, FT);
-            case 12: return launch_thermal_s<12>(c, Q, B, FT);
-            case 16: return launch_thermal_s<16>(c, Q, B, FT);
-            case 20: return launch_thermal_s<20>(c, Q, B, FT);
+            case 6: return launch_thermal_s<6, NoU>(c, Q, B, FT);
+            case 8: return launch_thermal_s<8, NoU>(c, Q, B, FT);
+            case 12: return launch_thermal_s<12, NoU>(c, Q, B, FT);
+            case 16: return launch_thermal_s<16, NoU>(c, Q, B, FT);
+            case 20: return launch_thermal_s<20, NoU>(c, Q, B, FT);
             default: break;
             }
         }
@@ -834,23 +834,23 @@ wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
     if (thermal_lds_bytes(32, 8, TZ, Rr, sizeof(R)) <= LDS_MAX) {
         if constexpr (TZ == 2) {
             switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1>(c, Q, B, FT);
-            case 2: return launch_thermal_r<R, TZ, 2>(c, Q, B, FT);
-            case 3: return launch_thermal_r<R, TZ, 3>(c, Q, B, FT);
-            case 4: return launch_thermal_r<R, TZ, 4>(c, Q, B, FT);
-            case 5: return launch_thermal_r<R, TZ, 5>(c, Q, B, FT);
+            case 1: return launch_thermal_r<R, TZ, 1, NoU>(c, Q, B, FT);
+            case 2: return launch_thermal_r<R, TZ, 2, NoU>(c, Q, B, FT);
+            case 3: return launch_thermal_r<R, TZ, 3, NoU>(c, Q, B, FT);
+            case 4: return launch_thermal_r<R, TZ, 4, NoU>(c, Q, B, FT);
+            case 5: return launch_thermal_r<R, TZ, 5, NoU>(c, Q, B, FT);
             default: break;
             }
         } else {
             switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1>(c, Q, B, FT);
-            case 2: return launch_thermal_r<R, TZ, 2>(c, Q, B, FT);
-            case 3: return launch_thermal_r<R, TZ, 3>(c, Q, B, FT);
-            case 4: return launch_thermal_r<R, TZ, 4>(c, Q, B, FT);
-            case 5: return launch_thermal_r<R, TZ, 5>(c, Q, B, FT);
-            case 6: return launch_thermal_r<R, TZ, 6>(c, Q, B, FT);
-            case 7: return launch_thermal_r<R, TZ, 7>(c, Q, B, FT);
-            case 8: return launch_thermal_r<R, TZ, 8>(c, Q, B, FT);
+            case 1: return launch_thermal_r<R, TZ, 1, NoU>(c, Q, B, FT);
+            case 2: return launch_thermal_r<R, TZ, 2, NoU>(c, Q, B, FT);
+            case 3: return launch_thermal_r<R, TZ, 3, NoU>(c, Q, B, FT);
+            case 4: return launch_thermal_r<R, TZ, 4, NoU>(c, Q, B, FT);
+            case 5: return launch_thermal_r<R, TZ, 5, NoU>(c, Q, B, FT);
+            case 6: return launch_thermal_r<R, TZ, 6, NoU>(c, Q, B, FT);
+            case 7: return launch_thermal_r<R, TZ, 7, NoU>(c, Q, B, FT);
+            case 8: return launch_thermal_r<R, TZ, 8, NoU>(c, Q, B, FT);
             default: break;
             }
         }
@@ -859,7 +859,7 @@ wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
     const double s = c->prm.sigma;
     const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8;
     return launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL((k_thermal<R>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, c->pad,
+        hipLaunchKernelGGL((k_thermal<R, NoU>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, c->pad,
                            (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
                            (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, Q, B, FT);
     });
@@ -987,9 +987,8 @@ wdlb_status conduction_steps(wdlb_ctx *c, const double *h_n, double *h_T, double
 // updated in place.  The step's kernels
 // with the mean-field and viscous/SMDB kernels launched apart:
 //   k_moments, k_density, k_meanfield;
-//   k_ru_rest     the velocity of the padded (rho, u1) array set to zero;
 //   k_pad         T over the density array (no longer needed);
-//   k_thermal     F^T, B and the conduction part of Q (all three at u = 0:
+//   k_thermal     F^T, B and the conduction part of Q (the variant at u = 0:
 //                 they depend on n and T alone) into the next parity's h
 //                 array (rewritten by the collision only after they are read);
 //   k_th_u1       F^mf <- theta F^mf, u1 = j/rho + (g + theta F^mf + F^T)/2
@@ -1035,10 +1034,9 @@ wdlb_status thermal_flow_pass(wdlb_ctx *c, R *T, int nsub)
     } reset{c};
     c->shell_part = 1;
     if ((st = launch_shells<R>(c)) != WDLB_OK) return st;
-    hipLaunchKernelGGL((k_ru_rest<R>), grid1(pd.NP, bs), dim3(bs), 0, c->stream, pd.NP, (V4<R> *)c->ru1_p);
     hipLaunchKernelGGL((k_pad<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, (R *)c->rho_p);
     HIPCHK(c, hipGetLastError());
-    if ((st = launch_thermal<R>(c, Qf, Bf, FT)) != WDLB_OK) return st;
+    if ((st = launch_thermal<R, true>(c, Qf, Bf, FT)) != WDLB_OK) return st;
     hipLaunchKernelGGL((k_th_u1<R>), grid, dim3(bs), 0, c->stream, g, pd, (const R *)T, kT, (const R *)c->jx,
                        (const R *)c->jy, (const R *)c->jz, (const R *)FT, R(p.g[0]), R(p.g[1]), R(p.g[2]),
                        (V4<R> *)c->fmf, (V4<R> *)c->ru1_p, c->flag);
