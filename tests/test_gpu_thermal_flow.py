@@ -8,10 +8,10 @@ force is recovered from the step's total force by a subtraction; FP64
 round-off).  FP32 storage (both local arithmetics): the populations to 1e-5
 of their largest value (FP32 storage, a few 1e-8 per step, and shell sums
 that cancel to many times the rounding of their largest term; measured
-<= 6e-7 over four steps), T to 1e-6 of itself (stored in FP32, 6e-8, and
+<= 5.1e-7 over four steps), T to 1e-6 of itself (stored in FP32, 6e-8, and
 changed each step by the work of a velocity carrying that rounding;
-measured <= 1.5e-7) and its change to 2e-5 of the largest change (measured
-<= 9.3e-7), the bars of the FP32 conduction at rest.
+measured <= 1.2e-7) and its change to 2e-5 of the largest change (measured
+<= 7.9e-7), the bars of the FP32 conduction at rest.
 """
 import math
 import sys
