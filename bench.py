@@ -248,9 +248,12 @@ def transport_bench(parts=("bulk", "sound", "slit")):
     effective viscosity of 16x16xH slits at sigma = 8 for eta = 0.11 and 0.32
     (run to steady state); and the collisional thermal conductivity and the
     heat-flux correction coefficient of the sigma = 8 fluid from its thermal
-    fields at two long temperature waves."""
+    fields at two long temperature waves; and the heat mode of the coupled
+    thermal flow (a temperature wave at constant pressure, L = 128) against
+    lambda q^2 / (n c_p)."""
     from paper_1304_7880_amd import transport, wdlb
     from paper_1304_7880_amd.workloads import BULK_128, BULK_ETAS
+    HEAT_ETAS = BULK_ETAS
     w = BULK_128
     bulk = []
     for eta in (BULK_ETAS if "bulk" in parts else ()):
@@ -299,6 +302,16 @@ def transport_bench(parts=("bulk", "sound", "slit")):
                "lam_total_tau1_c1exp22": round(r.lam_total(1.0, 4.0), 8)}
         thermal.append(row)
         print(json.dumps({"thermal_row": row}), file=sys.stderr, flush=True)
+    heat = []
+    for eta in (HEAT_ETAS if "heatmode" in parts else ()):
+        try:
+            h = transport.heat_mode(eta, sigma=8.0)
+            row = {"eta": eta, "rate": h.rate, "rate_rest_over_gamma": h.rate_rest / h.gamma, "ratio": h.ratio,
+                   "gamma": h.gamma, "lam_eff": h.lam_eff}
+        except wdlb.WdlbError as e:
+            row = {"eta": eta, "error": str(e)}
+        heat.append(row)
+        print(json.dumps({"heat_row": row}), file=sys.stderr, flush=True)
     slits = []
     for eta in ((0.11, 0.32) if "slit" in parts else ()):
         for H in (16, 32, 64, 128, 200):
@@ -313,7 +326,7 @@ def transport_bench(parts=("bulk", "sound", "slit")):
             "unit": "lattice units", "dtype": "fp32", "data": "synthetic",
             "config": {"workload": f"{w.name}, shear 5000 steps, sound 2000 steps; slits 16x16xH, sigma=8, tau=1, "
                                    "g_x=1e-6"},
-            "bulk": bulk, "sound": sound, "slit": slits, "thermal": thermal}
+            "bulk": bulk, "sound": sound, "slit": slits, "thermal": thermal, "heatmode": heat}
 
 
 SHELL_OPS_PER_OFFSET = 26.0   # VALU operations per shell offset counted for the method's shell sums
@@ -520,7 +533,8 @@ def main():
                     help="time only the coupled thermal flow on the workload's lattice (storage as --precision: "
                          "fp64, fp32 or fp32_local64); one JSON line")
     ap.add_argument("--transport", nargs="?", const="bulk,sound,slit", default=None, metavar="PARTS",
-                    help="run the transport experiments instead (comma list of bulk, sound, slit, thermal; "
+                    help="run the transport experiments instead (comma list of bulk, sound, slit, thermal, "
+                         "heatmode; "
                          "default bulk, sound, slit); "
                          "one JSON line")
     args = ap.parse_args()
@@ -540,8 +554,8 @@ def main():
     torch.cuda.set_device(0)
     if args.transport:
         parts = tuple(x for x in args.transport.split(",") if x)
-        if not parts or set(parts) - {"bulk", "sound", "slit", "thermal"}:
-            sys.exit("--transport takes a comma list of bulk, sound, slit, thermal")
+        if not parts or set(parts) - {"bulk", "sound", "slit", "thermal", "heatmode"}:
+            sys.exit("--transport takes a comma list of bulk, sound, slit, thermal, heatmode")
         print(json.dumps(transport_bench(parts)), flush=True)
         return
     stream = torch.cuda.current_stream()

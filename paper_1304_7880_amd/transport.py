@@ -296,3 +296,51 @@ def thermal_conduction_decay(eta, sigma=8.0, lengths=(128, 256), eps=1e-4, T0=1.
     sec4 = (2.5 * n0 * T0 / omega0 + 8.0 * math.pi / 3.0 * T0 * n0 * n0 * g * sigma ** 3 * r1 / (2.0 * omega0)
             + 2.0 / 3.0 * math.sqrt(math.pi * T0) * g * n0 * n0 * sigma ** 4 * r2)
     return ConductionDecay(eta, tuple(qs), tuple(lam), long_wave_limit(qs, lam), sec4, tuple(dec))
+
+
+@dataclass
+class HeatMode:
+    eta: float
+    q: float                 # 2 pi / L
+    rate: float              # measured per-step decay rate of the temperature wave at constant pressure
+    rate_rest: float         # per-step rate of the same wave in the fluid at rest (conduction at rest)
+    gamma: float             # c_ad^2 / c_T^2 of the Carnahan-Starling fluid
+    ratio: float             # rate / (rate_rest / gamma): 1 when the heat mode decays at lambda q^2 / (n c_p)
+    lam_eff: float           # rate n c_p / q^2, c_p = (3/2) gamma: the conductivity the coupled flow shows
+
+
+def heat_mode(eta, sigma=8.0, L=128, tau=1.0, eps=1e-3, steps=600, every=5, skip=100, nsub=4, nxy=4,
+              precision="fp64") -> HeatMode:
+    """The heat mode of the coupled thermal flow (wdlb_step_thermal): a
+    temperature wave kT (1 + eps sin(q z)) at constant pressure (dn/n =
+    -(Z / d(nZ)/dn) dT/T, at rest) in a periodic nxy x nxy x L box; its
+    amplitude's decay rate over [skip, steps] against the rate of the same
+    wave at rest and uniform density (wdlb_conduction_at_rest, 100 steps of
+    dt = 0.1) divided by gamma = c_ad^2 / c_T^2, the hydrodynamic heat-mode
+    rate lambda q^2 / (n c_p)."""
+    KT = 1.0 / 3.0
+    n0 = packing_to_density(eta, sigma)
+    Z = (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+    cT2 = carnahan_starling_c2(eta)
+    gamma = (cT2 + 2.0 / 3.0 * KT * Z * Z) / cT2
+    q = 2.0 * math.pi / L
+    z = np.arange(L, dtype=np.float64)
+    s = np.sin(q * z)
+    m = nxy * nxy
+    sr = np.repeat(s, m)
+    ctx = wdlb.Context(nxy, nxy, L, False, precision, sigma, eta, tau, (0.0, 0.0, 0.0))
+    T = KT * (1.0 + eps * sr)
+    dt, k = 0.1, 100
+    Tk = ctx.conduction_at_rest(np.full(L * m, n0), T, 1.0 / tau, dt, k)
+    rate_rest = -((float((Tk - KT) @ sr) / float((T - KT) @ sr)) ** (1.0 / k) - 1.0) / dt
+    ctx.init_thermal(np.repeat(n0 * (1.0 - Z / (cT2 / KT) * eps * s), m), np.zeros(3 * L * m), T)
+    ts, amps = [], []
+    for t in range(0, steps + 1, every):
+        ts.append(t)
+        amps.append(float((ctx.read_temperature() - KT) @ sr))
+        ctx.step_thermal(every, nsub)
+    ctx.destroy()
+    ts, amps = np.array(ts, dtype=np.float64), np.array(amps)
+    sel = ts >= skip
+    rate = -float(np.polyfit(ts[sel], np.log(amps[sel]), 1)[0])
+    return HeatMode(eta, q, rate, rate_rest, gamma, rate / (rate_rest / gamma), rate * n0 * 1.5 * gamma / (q * q))
