@@ -226,12 +226,14 @@ wdlb_status wdlb_conduction_at_rest(wdlb_ctx *ctx, const double *h_n, double *h_
 /* The coupled thermal flow: the step with a local temperature T(r), a
  * hybrid of the paper's isothermal scheme (Sec. 5) and its non-isothermal
  * fields (Sec. 3) and energy balance (Sec. 2, eq. energyequation).  With
- * theta = T / kT at each node the step's mean-field force and the velocity
- * u1 of the shell sums are scaled by theta, the viscous force by
- * sqrt(theta), A_ij by theta (Sec. 3 gives them as k_B T, sqrt(k_B T) and
- * k_B T times the isothermal sums), the thermal force F^T (eq.
- * thermalforce) is added to the force, and the collision relaxes towards
- * the equilibrium plus w_a rho (3/2)(theta - 1)(|c_a|^2 - 1).  After the
+ * theta = T / kT at each node the step's mean-field force is scaled by
+ * theta, the viscous force by sqrt(theta), A_ij by theta (Sec. 3 gives them
+ * as k_B T, sqrt(k_B T) and k_B T times the isothermal sums), the thermal
+ * force F^T (eq. thermalforce, from n and T alone) is added to the force,
+ * the velocity u1 = j/rho + (g + theta F^mf + F^T)/2 of the viscous and
+ * thermal sums carries every force known before them, and the collision
+ * relaxes towards the equilibrium plus w_a rho (3/2)(theta - 1)(|c_a|^2 -
+ * 1).  After the
  * stream T advances by one step of
  *   dT/dt = -u.grad T + (2/(3n)) (-div q - P:grad u + Q)
  * with q of eq. qexplicit (omega0 = 1/tau), P of eqs. pexplicit and
