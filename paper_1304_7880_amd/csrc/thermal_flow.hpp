@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_th_init(Geom g, const V4<R> *__restrict
     }
 }
 
-// after the mean-field and the first thermal kernel: F^mf <- theta F^mf and
+// after the mean-field kernel and the thermal kernel at u = 0: F^mf <- theta F^mf and
 // u1 = j/rho + (g + theta F^mf + F^T)/2 (every force known before the
 // viscous sums) into the padded (rho, u1) array with its images; a
 // temperature that is not positive and finite raises FLAG_T
