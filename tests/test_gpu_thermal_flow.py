@@ -60,7 +60,12 @@ CASES = [
 
 
 BARS = {"fp64": (1e-11, 1e-11, 1e-9), "fp32": (1e-5, 1e-6, 2e-5), "fp32_local64": (1e-5, 1e-6, 2e-5)}
-FP32_CASES = [CASES[0], CASES[2], CASES[5]]
+FP32_CASES = [CASES[0], CASES[2], CASES[5],
+              # the compiled shells of sigma = 6 and 8 (FP32 only), ragged tiles
+              ("walled 36x10x26 sigma=6 (compiled shell)", (36, 10, 26), True, 6.0, 0.35, 0.8, (2e-5, 0.0, 0.0),
+               True, 2, 4, 0.1),
+              ("periodic 24x20x30 sigma=8 (compiled shell)", (24, 20, 30), False, 8.0, 0.25, 1.0, (0.0, 0.0, 0.0),
+               True, 2, 5, 0.1)]
 
 
 def _run_case(case, prec):
