@@ -11,7 +11,7 @@ that cancel to many times the rounding of their largest term; measured
 <= 5.1e-7 over four steps), T to 1e-6 of itself (stored in FP32, 6e-8, and
 changed each step by the work of a velocity carrying that rounding;
 measured <= 1.2e-7) and its change to 2e-5 of the largest change (measured
-<= 7.9e-7), the bars of the FP32 conduction at rest.
+<= 8.7e-7), the bars of the FP32 conduction at rest.
 """
 import math
 import sys
