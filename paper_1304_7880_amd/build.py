@@ -8,27 +8,45 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "wdlb.hip")
+# the library's translation units, compiled side by side, then linked
+SRCS = [os.path.join(HERE, "csrc", "wdlb.hip"), os.path.join(HERE, "csrc", "thermal_launch.hip")]
 LIB = os.path.join(HERE, "libwdlb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: hipcc would otherwise form them from
 # plain float code.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]
 
 
 def build(verbose: bool = False) -> str:
     """Always recompiles; returns the library path."""
+    objs = [os.path.splitext(src)[0] + ".o" for src in SRCS]
+    procs = []
+    for src, obj in zip(SRCS, objs):
+        cmd = [HIPCC] + FLAGS + ["-c", "-o", obj + ".tmp", src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = []
+    for src, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out + err)
+            failed.append(src)
+    if failed:
+        raise RuntimeError("hipcc failed for " + ", ".join(failed))
+    for obj in objs:
+        os.replace(obj + ".tmp", obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for " + SRC)
+        raise RuntimeError("hipcc failed to link " + LIB)
     os.replace(tmp, LIB)
     return LIB
 

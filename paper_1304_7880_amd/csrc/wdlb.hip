@@ -1,107 +1,13 @@
 // wdlb.hip -- host side of the MI355X (gfx950) WDLB library behind the C
 // ABI of include/wdlb.h: workspace layout, stencil tables, kernel launches
 // (kernels.hpp), reads, checkpoints and event timing.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <mutex>
-#include <string>
-#include <type_traits>
-#include <vector>
-
-#include "../../include/wdlb.h"
-#include "kernels.hpp"
+#include "context.hpp"
 #include "thermal.hpp"
 #include "thermal_flow.hpp"
 
-using namespace wdlb;
-
-namespace {
-constexpr double KT = 1.0 / 3.0;
-constexpr int MAX_QUADS = 4096;
-constexpr int MAX_BALL = 8192;
-constexpr int MAX_REACH = 17;
-constexpr double MAX_SIGMA = 16.0;
-}  // namespace
-
-// ===========================================================================
-// host side
-// ===========================================================================
-struct wdlb_ctx {
-    wdlb_lattice_desc desc;
-    wdlb_params prm;
-    hipStream_t stream;
-    Geom g;
-    Pad pad;
-    int prec;          // wdlb_precision requested (storage and local arithmetic)
-    int store;         // its storage: WDLB_FP64, WDLB_FP32 or WDLB_BF16_NEQ
-    size_t rsize;      // bytes of one real (compute type)
-    size_t hsize;      // bytes of one stored h
-    int hplanes;       // planes of h per node (19; 23 in the BF16 mode)
-    char *ws;
-    size_t ws_bytes;
-    // carved device arrays
-    void *ru[2], *h[2];                  // state: (rho, u*) and deviations, two parities
-    void *rho_p, *gam_p, *ru1_p;  // padded per-step arrays
-    void *jx, *jy, *jz, *fmf, *F, *A, *u_rd, *rho_rd;
-    void *scratch;                        // >= 8 N reals, free between steps
-    size_t padded_bytes;                  // bytes from rho_p to the end of ru1_p
-    double *planes;
-    int *flag;
-    void *quads;
-    int *qstart;
-    int *ball;
-    ZPlane *zp_dev;                       // per-plane table (used by stacked lattices)
-    int nq, nball, rb, reach;  // quad count; ball size and reach; shell reach
-    int dtile;                 // k_density tile (index into DENSITY_TILES)
-    double wS;         // 4 pi / |S|
-    int tile;          // contact-shell tile variant of the viscous/SMDB kernel (index into SHELL_TILES)
-    int tile_mf;       // and of the mean-field kernel
-    int tile_req;      // requested variant, -1 = automatic
-    int spec_s2;       // 2 sigma of the specialised shell kernels in use, 0 = generic
-    int spec_b2;       // 2 sigma of the specialised density kernel in use, 0 = generic
-    int cur;
-    // HIP graphs of two steps (one per starting parity), replayed by
-    // wdlb_step; captured on a private stream, launched on the caller's
-    bool graphs = true;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int graph_nz_run = -1;
-    int nz_run;        // planes the step kernels process (nz; fewer in a partly filled stacked lattice)
-    int64_t step;
-    bool inited;
-    int static_dev = -1;  // device whose static workspace this context holds (wdlb_create_static), else -1
-    int shell_part = 3;   // bit 0: launch the mean-field kernel, bit 1: the viscous/SMDB kernel (the thermal step runs them apart)
-    void *shell_trace = nullptr;  // the viscous/SMDB kernel's trace sums go here when set (the thermal step)
-    std::string err;
-    // event timing of the step kernels
-    int prof = 0;  // bit k: time kernel k
-    std::vector<hipEvent_t> ev_free;
-    struct Pending {
-        int k;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> pending;
-    double prof_ms[WDLB_NKERNELS] = {0};
-    int64_t prof_n[WDLB_NKERNELS] = {0};
-};
-
 namespace {
 
-wdlb_status fail(wdlb_ctx *c, wdlb_status st, const std::string &msg)
-{
-    if (c) c->err = msg;
-    return st;
-}
-
-#define HIPCHK(ctx, call)                                                                                  \
-    do {                                                                                                   \
-        hipError_t e_ = (call);                                                                            \
-        if (e_ != hipSuccess) return fail(ctx, WDLB_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+using wdlb_lib::launch_thermal;
 
 bool desc_ok(const wdlb_lattice_desc *d)
 {
@@ -267,7 +173,6 @@ constexpr int L1G_TILE = 6;
 constexpr int L1G_MIN_S2 = 16;
 constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
 static_assert(NTILES == WDLB_NTILES, "the header's variant count");
-constexpr size_t LDS_MAX = 160 * 1024;
 
 // k_density tiles: 32 x 8 x 2 while its LDS stays within 64 KB (several
 // blocks per CU), else 16 x 8 x 1; lattices at most 16 wide take 16 x 16 x 2
@@ -310,14 +215,6 @@ constexpr int pick_tile(int reach, size_t rbytes, int nx)
     return pick_tile_wide(reach, rbytes);
 }
 
-// 2 sigma of the shells and balls compiled into the library, else 0
-int specialised_s2(double sigma)
-{
-    static const int S2[] = {6, 8, 12, 16, 20};
-    for (int s2 : S2)
-        if (sigma == 0.5 * s2) return s2;
-    return 0;
-}
 
 // compiled kernels exist for the wide automatic tiles of every compiled
 // shell (when gamma is staged in LDS), and for the narrow tiles at sigma = 4
@@ -423,62 +320,10 @@ wdlb_status tables(wdlb_ctx *c)
     return upload_tables<float>(c);
 }
 
-inline dim3 grid1(long long N, int bs) { return dim3((unsigned)((N + bs - 1) / bs)); }
 
-enum { K_MOMENTS = 0, K_DENSITY, K_MEANFIELD, K_SHELL, K_COLLIDE, K_THERMAL };
 const char *const KNAMES[WDLB_NKERNELS] = {"k_moments", "k_density", "k_meanfield", "k_shell", "k_collide",
                                            "k_thermal"};
 
-// Timing events are created without the system-scope fence: a default event
-// writes back and invalidates the caches when it is recorded, which slows
-// the timed kernel's successor and inflates the measured times.  prof_flush
-// synchronises the stream before it reads them, so no fence is needed.
-hipEvent_t take_event(wdlb_ctx *c)
-{
-    if (c->ev_free.empty()) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
-        return e;
-    }
-    hipEvent_t e = c->ev_free.back();
-    c->ev_free.pop_back();
-    return e;
-}
-
-wdlb_status prof_flush(wdlb_ctx *c)
-{
-    if (c->pending.empty()) return WDLB_OK;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto &p : c->pending) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-            c->prof_ms[p.k] += ms;
-            c->prof_n[p.k] += 1;
-        }
-        c->ev_free.push_back(p.a);
-        c->ev_free.push_back(p.b);
-    }
-    c->pending.clear();
-    return WDLB_OK;
-}
-
-// launch through this wrapper so that profiling can bracket the kernel
-template <typename L>
-wdlb_status launch(wdlb_ctx *c, int k, L &&fn)
-{
-    if (!(c->prof >> k & 1)) {
-        fn();
-        return WDLB_OK;
-    }
-    hipEvent_t a = take_event(c), b = take_event(c);
-    if (!a || !b) return fail(c, WDLB_E_HIP, "hipEventCreate failed");
-    HIPCHK(c, hipEventRecord(a, c->stream));
-    fn();
-    HIPCHK(c, hipEventRecord(b, c->stream));
-    c->pending.push_back({k, a, b});
-    if (c->pending.size() >= 4096) return prof_flush(c);
-    return WDLB_OK;
-}
 
 template <typename R, int TX, int TY, int TZ, int NR, int NG>
 wdlb_status launch_shell_pair(wdlb_ctx *c)
@@ -768,101 +613,6 @@ size_t state_bytes(const wdlb_ctx *c)
 {
     const size_t N = (size_t)c->g.N;
     return sizeof(StateHeader) + 4 * c->rsize * N + (size_t)c->hplanes * c->hsize * N;
-}
-
-// The thermal-field kernels: compiled for the shell (FP32, compiled sigma),
-// else table-driven on LDS-ring tiles (32 x 8 x 2 in FP32, 32 x 8 x 1 in
-// FP64) where the two rings fit, else the cache kernel.
-template <typename R, int TZ, int NR, bool NoU>
-wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
-{
-    const Geom g = c->g;
-    const double s = c->prm.sigma;
-    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8, tz = (g.nz + TZ - 1) / TZ;
-    const size_t lds = thermal_lds_bytes(32, 8, TZ, c->reach, sizeof(R));
-    auto kern = k_thermal_r<R, 32, 8, TZ, NR, NoU>;
-    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    return launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(32 * 8 * TZ), lds, c->stream, g, c->pad,
-                           c->reach, (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, (const int *)c->qstart, R(s * s), tx, ty, tz, Q, B, FT);
-    });
-}
-
-// compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
-// sigma = 10 their two rings (75 KB) leave room for two blocks per CU
-template <int S2, bool NoU>
-wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
-{
-    constexpr int TX = 32, TY = 16, TZ = 1, NT = TX * TY * TZ;
-    constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
-    static_assert(thermal_lds_bytes(TX, TY, TZ, RC, 4) <= LDS_MAX, "rings fit in LDS");
-    if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
-    const Geom g = c->g;
-    const double s = c->prm.sigma;
-    const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
-    const size_t lds = thermal_lds_bytes(TX, TY, TZ, RC, 4);
-    auto kern = k_thermal_s<float, S2, TX, TY, TZ, NR, NoU>;
-    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    return launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
-                           (const V4<float> *)c->ru1_p, (const float *)c->rho_p, (const float *)c->gam_p,
-                           float(s * s), tx, ty, tz, Q, B, FT);
-    });
-}
-
-template <typename R, bool NoU = false>
-wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
-{
-    if constexpr (std::is_same<R, float>::value) {
-        // the buffer loads of the contact values take a lane offset below
-        // 2^31 bytes into one padded sub-lattice; a forced shell tile
-        // (wdlb_set_tile >= 0) selects the table-driven kernels here too
-        if (c->tile_req < 0 && 4.0 * (double)c->pad.NP < 2.0e9) {
-            switch (specialised_s2(c->prm.sigma)) {
-            case 6: return launch_thermal_s<6, NoU>(c, Q, B, FT);
-            case 8: return launch_thermal_s<8, NoU>(c, Q, B, FT);
-            case 12: return launch_thermal_s<12, NoU>(c, Q, B, FT);
-            case 16: return launch_thermal_s<16, NoU>(c, Q, B, FT);
-            case 20: return launch_thermal_s<20, NoU>(c, Q, B, FT);
-            default: break;
-            }
-        }
-    }
-    constexpr int TZ = std::is_same<R, float>::value ? 2 : 1;
-    const int Rr = c->reach, LP = (32 + 2 * Rr) * (8 + 2 * Rr), nr = (LP + 32 * 8 * TZ - 1) / (32 * 8 * TZ);
-    if (thermal_lds_bytes(32, 8, TZ, Rr, sizeof(R)) <= LDS_MAX) {
-        if constexpr (TZ == 2) {
-            switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1, NoU>(c, Q, B, FT);
-            case 2: return launch_thermal_r<R, TZ, 2, NoU>(c, Q, B, FT);
-            case 3: return launch_thermal_r<R, TZ, 3, NoU>(c, Q, B, FT);
-            case 4: return launch_thermal_r<R, TZ, 4, NoU>(c, Q, B, FT);
-            case 5: return launch_thermal_r<R, TZ, 5, NoU>(c, Q, B, FT);
-            default: break;
-            }
-        } else {
-            switch (nr) {
-            case 1: return launch_thermal_r<R, TZ, 1, NoU>(c, Q, B, FT);
-            case 2: return launch_thermal_r<R, TZ, 2, NoU>(c, Q, B, FT);
-            case 3: return launch_thermal_r<R, TZ, 3, NoU>(c, Q, B, FT);
-            case 4: return launch_thermal_r<R, TZ, 4, NoU>(c, Q, B, FT);
-            case 5: return launch_thermal_r<R, TZ, 5, NoU>(c, Q, B, FT);
-            case 6: return launch_thermal_r<R, TZ, 6, NoU>(c, Q, B, FT);
-            case 7: return launch_thermal_r<R, TZ, 7, NoU>(c, Q, B, FT);
-            case 8: return launch_thermal_r<R, TZ, 8, NoU>(c, Q, B, FT);
-            default: break;
-            }
-        }
-    }
-    const Geom g = c->g;
-    const double s = c->prm.sigma;
-    const int tx = (g.nx + 31) / 32, ty = (g.ny + 7) / 8;
-    return launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL((k_thermal<R, NoU>), dim3((unsigned)(tx * ty * g.nz)), dim3(256), 0, c->stream, g, c->pad,
-                           (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p,
-                           (const Quad<R> *)c->quads, c->nq, R(s * s), tx, ty, Q, B, FT);
-    });
 }
 
 // Thermal fields at given n, u, T.  The device part (thermal_launch) reads
