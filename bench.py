@@ -435,7 +435,7 @@ def thermal_flow_bench(w, prec, steps=3, warmup=1, nsub=4):
     nS = shell_size(w.sigma)
     peak = PEAK_FP64_VECTOR_TFLOPS if prec == "fp64" else PEAK_FP32_VECTOR_TFLOPS
     names = {"k_shell": "k_shell_s" if spec else "k_shell",
-             "k_thermal": "k_thermal_s" if (spec and prec != "fp64") else "k_thermal_r"}
+             "k_thermal": "k_thermal_s0" if (spec and prec != "fp64") else "k_thermal_r"}
     out = {"workload": w.name, "precision": PRECISION_LABEL[prec], "nsub": nsub, "steps": steps,
            "ms_per_step": round(ms, 3), "mlups": round(w.N / (ms * 1e-3) / 1e6, 2),
            "kernels_ms_per_step": {k: round(v, 4) for k, v in kst.items()},

@@ -361,6 +361,204 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V
     th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, NoU ? R(0) : aV, Qo, Bo, FTo);
 }
 
+// ring of density planes filled from the (rho, u) array's first component:
+// the plane ring of PlaneRing<R, R> (same window, same element order) with
+// 4-byte LDS entries
+template <typename R, int NT, int NR>
+struct RhoRing {
+    int LX, LP;
+    int off[NR];
+    R st[2][NR];  // two staging sets: one in flight while the other is stored
+
+    __device__ __forceinline__ void setup(const Pad &p, int Rr, int TX, int TY, int x0, int y0)
+    {
+        LX = TX + 2 * Rr;
+        LP = LX * (TY + 2 * Rr);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int e = min((int)threadIdx.x + k * NT, LP - 1);
+            const int X = min(max(x0 - Rr + e % LX + p.P, 0), p.PX - 1);
+            const int Y = min(max(y0 - Rr + e / LX + p.P, 0), p.PY - 1);
+            off[k] = Y * p.PX + X;
+        }
+    }
+    __device__ __forceinline__ void fetch_to(R (&d)[NR], const V4<R> *__restrict__ src, const Pad &p, int pz)
+    {
+        const long long zb = (long long)min(max(pz + p.P, 0), p.PZ - 1) * p.PXY;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) d[k] = src[zb + off[k]].x;
+    }
+    template <int S>
+    __device__ __forceinline__ void fetch(const V4<R> *__restrict__ src, const Pad &p, int pz)
+    {
+        fetch_to(st[S], src, p, pz);
+    }
+    __device__ __forceinline__ void store_all(const R (&d)[NR], R *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) win[slot * LP + min((int)threadIdx.x + k * NT, LP - 1)] = d[k];
+    }
+    template <int S>
+    __device__ __forceinline__ void store(R *win, int slot)
+    {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int e = (int)threadIdx.x + k * NT;
+            if (e < LP) win[slot * LP + e] = st[S][k];
+        }
+    }
+};
+
+// LDS of k_thermal_s0 on TX x TY x 1 tiles: the density and T rings (two
+// planes each), then the contact-value ring (two slices of four sub-lattices)
+__host__ __device__ constexpr size_t thermal0_lds_bytes(int TX, int TY, int Rr, size_t rbytes)
+{
+    return (size_t)2 * (TX + 2 * Rr) * (TY + 2 * Rr) * 2 * rbytes + (size_t)2 * 4 * (TX + Rr) * (TY + Rr) * rbytes;
+}
+template <int TX, int TY, int RC>
+struct Thermal0Tile {
+    static constexpr int NT = TX * TY;
+    static constexpr int NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
+    static constexpr int NG = (4 * (TX + RC) * (TY + RC) + NT - 1) / NT;
+};
+
+// The thermal sums at u = 0 compiled for the shell of 2 sigma = S2 (FP32) on
+// TX x TY x 1 tiles: F^T, B and the conduction part of Q, the velocity not
+// read.  The density, T and the contact values all come from LDS rings
+// that advance along e_z (the contact values as in the mean-field kernel,
+// and with its prefetch depth 2: each step loads what the next one stores),
+// so the texture path carries only the ring fills; the arithmetic repeats
+// k_thermal_s's term for term (the same bits).
+template <typename R, int S2, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_thermal_s0(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
+                                                       const R *__restrict__ T_p, const R *__restrict__ gam_p, R s2,
+                                                       int tiles_x, int tiles_y, int tiles_z, R *__restrict__ Qo,
+                                                       R *__restrict__ Bo, R *__restrict__ FTo)
+{
+    using SH = Shell<S2>;
+    constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
+    constexpr int NT = TX * TY, NS = 2, NR = Thermal0Tile<TX, TY, RC>::NR, NG = Thermal0Tile<TX, TY, RC>::NG;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const TileCoord tc = tile_coord<TX, TY, 1, true>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0;
+    const bool valid = x < g.nx && y < g.ny && z < g.nz;
+    RhoRing<R, NT, NR> rr;
+    rr.setup(p, RC, TX, TY, tc.x0, tc.y0);
+    PlaneRing<R, R, NT, NR> tr;
+    tr.setup(p, RC, TX, TY, tc.x0, tc.y0);
+    GammaRing<R, NT, NG> gr;
+    gr.setup(p, RC, TX, TY, tc.x0, tc.y0);
+    R *rwin = reinterpret_cast<R *>(lds_raw);
+    R *twin = rwin + NS * rr.LP;
+    R *gwin = twin + NS * rr.LP;
+    {
+        R rst[NR], tst[1][NR], gst[NG];
+        rr.fetch_to(rst, ru_p, p, tc.z0 - RC);
+        tr.fetch_to(tst, T_p, p, tc.z0 - RC);
+        gr.fetch_to(gst, gam_p, p, tc.z0, -RC);
+        // what step -RC stores at its end (prefetch depth 2, as the mean-field kernel)
+        rr.template fetch<0>(ru_p, p, tc.z0 - RC + 1);
+        tr.template fetch<0, false>(T_p, p, tc.z0 - RC + 1);
+        gr.template fetch<0, false>(gam_p, p, tc.z0, -RC + 1);
+        rr.store_all(rst, rwin, 0);
+        tr.store_all(tst, twin, 0);
+        gr.store_all(gst, gwin, (64 - RC) % 2);
+    }
+    __syncthreads();
+    const int lbase = (tc.ly + RC) * LX + (tc.lx + RC), gcen = (tc.ly + O) * LXg + (tc.lx + O);
+    const int gbase = pidx(p, min(x, g.nx - 1), min(y, g.ny - 1), min(z, g.nz - 1));
+    const R n0 = ru_p[gbase].x, T0 = T_p[gbase];
+    R ax = 0, ay = 0, az = 0, aT = 0;
+    static_for<-RC, RC + 1>([&](auto ci) __attribute__((always_inline)) {
+        constexpr int c = decltype(ci)::value;
+        constexpr int S = (c + RC) & 1;
+        if constexpr (c + 1 < RC) {  // for the store at the end of step c + 1
+            rr.template fetch<S ^ 1>(ru_p, p, tc.z0 + c + 2);
+            tr.template fetch<S ^ 1, false>(T_p, p, tc.z0 + c + 2);
+            gr.template fetch<S ^ 1, false>(gam_p, p, tc.z0, c + 2);
+        }
+        const R *pc = rwin + ((c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
+        const R *tcp = twin + ((c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
+        const R *gc = gwin + ((c + 64) % 2) * gr.LS + gcen - (O + O * LXg);
+        __amdgpu_buffer_rsrc_t gnone[4];  // unused: the contact values come from LDS
+        static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
+            constexpr CQuad Q = SH::T.q[decltype(qi)::value];
+            constexpr int a = Q.a, b = Q.b;
+#define WDLB_TGAM(SA, SB) gamma_img<R, true, O, LXg, LG, a, b, Q.h, SA, SB>(gc, gnone, p.PX, 0u)
+            if constexpr (a == 0 && b == 0) {
+                R D;
+                {
+#pragma clang fp contract(off)
+                    const R G = WDLB_TGAM(1, 1) * pc[RC + RC * LX];
+                    D = G * (tcp[RC + RC * LX] - T0);
+                }
+                az += R(4 * Q.pz) * D;
+                aT += D;
+            } else if constexpr (a == 0) {  // images (0, b), (0, -b)
+                R dp, dm;
+                {
+#pragma clang fp contract(off)
+                    const R G0 = WDLB_TGAM(1, 1) * pc[RC + (RC + b) * LX];
+                    const R G2 = WDLB_TGAM(1, -1) * pc[RC + (RC - b) * LX];
+                    const R D0 = G0 * (tcp[RC + (RC + b) * LX] - T0), D2 = G2 * (tcp[RC + (RC - b) * LX] - T0);
+                    dp = D0 + D2;
+                    dm = D0 - D2;
+                }
+                ay += R(2 * Q.py) * dm;
+                az += R(2 * Q.pz) * dp;
+                aT += dp;
+            } else if constexpr (b == 0) {  // images (a, 0), (-a, 0)
+                R dp, dm;
+                {
+#pragma clang fp contract(off)
+                    const R G0 = WDLB_TGAM(1, 1) * pc[(RC + a) + RC * LX];
+                    const R G1 = WDLB_TGAM(-1, 1) * pc[(RC - a) + RC * LX];
+                    const R D0 = G0 * (tcp[(RC + a) + RC * LX] - T0), D1 = G1 * (tcp[(RC - a) + RC * LX] - T0);
+                    dp = D0 + D1;
+                    dm = D0 - D1;
+                }
+                ax += R(2 * Q.px) * dm;
+                az += R(2 * Q.pz) * dp;
+                aT += dp;
+            } else {
+                const R gm[4] = {WDLB_TGAM(1, 1), WDLB_TGAM(-1, 1), WDLB_TGAM(1, -1), WDLB_TGAM(-1, -1)};
+                const R rm[4] = {pc[(RC + a) + (RC + b) * LX], pc[(RC - a) + (RC + b) * LX],
+                                 pc[(RC + a) + (RC - b) * LX], pc[(RC - a) + (RC - b) * LX]};
+                const R tm[4] = {tcp[(RC + a) + (RC + b) * LX], tcp[(RC - a) + (RC + b) * LX],
+                                 tcp[(RC + a) + (RC - b) * LX], tcp[(RC - a) + (RC - b) * LX]};
+                R hx, hy, h0;
+                {
+#pragma clang fp contract(off)
+                    R D[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) D[m] = (gm[m] * rm[m]) * (tm[m] - T0);
+                    const R P1 = D[0] + D[1], M1 = D[0] - D[1], P2 = D[2] + D[3], M2 = D[2] - D[3];
+                    hx = M1 + M2;
+                    hy = P1 - P2;
+                    h0 = P1 + P2;
+                }
+                ax += R(Q.px) * hx;
+                ay += R(Q.py) * hy;
+                az += R(Q.pz) * h0;
+                aT += h0;
+            }
+#undef WDLB_TGAM
+        });
+        pin(ax);
+        pin(ay);
+        pin(az);
+        pin(aT);
+        if constexpr (c < RC) {
+            rr.template store<S>(rwin, (c + 1 + RC) % NS);
+            tr.template store<S>(twin, (c + 1 + RC) % NS);
+            gr.template store<S>(gwin, (c + 1 + 64) % 2);
+        }
+        __syncthreads();
+    });
+    if (!valid) return;
+    th_finish<R>(g, x, y, z, n0, T0, s2, ax, ay, az, aT, R(0), Qo, Bo, FTo);
+}
+
 // LDS bytes of k_thermal_r: the (rho, u) ring, then the T ring
 __host__ __device__ constexpr size_t thermal_lds_bytes(int TX, int TY, int TZ, int Rr, size_t rbytes)
 {

@@ -26,7 +26,8 @@ wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 }
 
 // compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
-// sigma = 10 their two rings (75 KB) leave room for two blocks per CU
+// sigma = 10 their two rings (75 KB) leave room for two blocks per CU; at
+// u = 0 k_thermal_s0 with the contact values in LDS as well (70 KB)
 template <int S2, bool NoU>
 wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
 {
@@ -37,8 +38,10 @@ wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
     const Geom g = c->g;
     const double s = c->prm.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
-    const size_t lds = thermal_lds_bytes(TX, TY, TZ, RC, 4);
-    auto kern = k_thermal_s<float, S2, TX, TY, TZ, NR, NoU>;
+    // at u = 0: the density, T and contact-value rings of k_thermal_s0
+    static_assert(thermal0_lds_bytes(TX, TY, RC, 4) <= LDS_MAX, "rings fit in LDS");
+    const size_t lds = NoU ? thermal0_lds_bytes(TX, TY, RC, 4) : thermal_lds_bytes(TX, TY, TZ, RC, 4);
+    auto kern = NoU ? k_thermal_s0<float, S2, TX, TY> : k_thermal_s<float, S2, TX, TY, TZ, NR, false>;
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
