@@ -344,3 +344,22 @@ def test_compiled_and_table_driven_kernels_give_the_same_bits(sigma):
         out.append((ctx.read_populations(), ctx.read_temperature()))
         ctx.destroy()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_allocation_free_context_steps_the_same():
+    """The coupled flow on a context made by wdlb_create_static (the
+    library's own device array as the workspace) gives the bits of a context
+    on a caller's workspace; T stays the caller's (FP32 storage, walled
+    17x11x15, sigma = 3, three steps)."""
+    from paper_1304_7880_amd import wdlb
+    nx, ny, nz, sigma, eta, tau = 17, 11, 15, 3.0, 0.3, 0.9
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=81)
+    T0 = random_temperature(nx, ny, nz, KT, 0.05, seed=82)
+    out = []
+    for static in (False, True):
+        ctx = wdlb.Context(nx, ny, nz, True, "fp32_local64", sigma, eta, tau, (1e-4, 0.0, 0.0), static=static)
+        ctx.init_thermal(n, u, T0)
+        ctx.step_thermal(3, 4)
+        out.append((ctx.read_populations(), ctx.read_temperature()))
+        ctx.destroy()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
