@@ -409,38 +409,40 @@ struct RhoRing {
     }
 };
 
-// LDS of k_thermal_s0 on TX x TY x 1 tiles: the density and T rings (two
-// planes each), then the contact-value ring (two slices of four sub-lattices)
-__host__ __device__ constexpr size_t thermal0_lds_bytes(int TX, int TY, int Rr, size_t rbytes)
+// LDS of k_thermal_s0 on TX x TY x TZ tiles: the density and T rings (TZ + 1
+// planes each), then the contact-value ring (2 TZ slices of four sub-lattices)
+__host__ __device__ constexpr size_t thermal0_lds_bytes(int TX, int TY, int TZ, int Rr, size_t rbytes)
 {
-    return (size_t)2 * (TX + 2 * Rr) * (TY + 2 * Rr) * 2 * rbytes + (size_t)2 * 4 * (TX + Rr) * (TY + Rr) * rbytes;
+    return (size_t)(TZ + 1) * (TX + 2 * Rr) * (TY + 2 * Rr) * 2 * rbytes +
+           (size_t)2 * TZ * 4 * (TX + Rr) * (TY + Rr) * rbytes;
 }
-template <int TX, int TY, int RC>
+template <int TX, int TY, int TZ, int RC>
 struct Thermal0Tile {
-    static constexpr int NT = TX * TY;
+    static constexpr int NT = TX * TY * TZ;
     static constexpr int NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
     static constexpr int NG = (4 * (TX + RC) * (TY + RC) + NT - 1) / NT;
 };
 
 // The thermal sums at u = 0 compiled for the shell of 2 sigma = S2 (FP32) on
-// TX x TY x 1 tiles: F^T, B and the conduction part of Q, the velocity not
+// TX x TY x TZ tiles: F^T, B and the conduction part of Q, the velocity not
 // read.  The density, T and the contact values all come from LDS rings
 // that advance along e_z (the contact values as in the mean-field kernel,
 // and with its prefetch depth 2: each step loads what the next one stores),
 // so the texture path carries only the ring fills; the arithmetic repeats
 // k_thermal_s's term for term (the same bits).
-template <typename R, int S2, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_thermal_s0(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
+template <typename R, int S2, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s0(Geom g, Pad p, const V4<R> *__restrict__ ru_p,
                                                        const R *__restrict__ T_p, const R *__restrict__ gam_p, R s2,
                                                        int tiles_x, int tiles_y, int tiles_z, R *__restrict__ Qo,
                                                        R *__restrict__ Bo, R *__restrict__ FTo)
 {
     using SH = Shell<S2>;
     constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, LXg = TX + RC, LG = LXg * (TY + RC);
-    constexpr int NT = TX * TY, NS = 2, NR = Thermal0Tile<TX, TY, RC>::NR, NG = Thermal0Tile<TX, TY, RC>::NG;
+    constexpr int NT = TX * TY * TZ, NS = TZ + 1, NSG = 2 * TZ;
+    constexpr int NR = Thermal0Tile<TX, TY, TZ, RC>::NR, NG = Thermal0Tile<TX, TY, TZ, RC>::NG;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const TileCoord tc = tile_coord<TX, TY, 1, true>(tiles_x, tiles_y, tiles_z);
-    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0;
+    const TileCoord tc = tile_coord<TX, TY, TZ, TZ == 1>(tiles_x, tiles_y, tiles_z);
+    const int x = tc.x0 + tc.lx, y = tc.y0 + tc.ly, z = tc.z0 + tc.lz;
     const bool valid = x < g.nx && y < g.ny && z < g.nz;
     RhoRing<R, NT, NR> rr;
     rr.setup(p, RC, TX, TY, tc.x0, tc.y0);
@@ -452,17 +454,26 @@ __global__ __launch_bounds__(TX *TY) void k_thermal_s0(Geom g, Pad p, const V4<R
     R *twin = rwin + NS * rr.LP;
     R *gwin = twin + NS * rr.LP;
     {
-        R rst[NR], tst[1][NR], gst[NG];
-        rr.fetch_to(rst, ru_p, p, tc.z0 - RC);
-        tr.fetch_to(tst, T_p, p, tc.z0 - RC);
-        gr.fetch_to(gst, gam_p, p, tc.z0, -RC);
+        // the first TZ planes and 2 TZ - 1 slices, all fetched before any is stored
+        R rst[TZ][NR], tst[TZ][1][NR], gst[2 * TZ - 1][NG];
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            rr.fetch_to(rst[k], ru_p, p, tc.z0 - RC + k);
+            tr.fetch_to(tst[k], T_p, p, tc.z0 - RC + k);
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * TZ - 1; ++j) gr.fetch_to(gst[j], gam_p, p, tc.z0, j - RC);
         // what step -RC stores at its end (prefetch depth 2, as the mean-field kernel)
-        rr.template fetch<0>(ru_p, p, tc.z0 - RC + 1);
-        tr.template fetch<0, false>(T_p, p, tc.z0 - RC + 1);
-        gr.template fetch<0, false>(gam_p, p, tc.z0, -RC + 1);
-        rr.store_all(rst, rwin, 0);
-        tr.store_all(tst, twin, 0);
-        gr.store_all(gst, gwin, (64 - RC) % 2);
+        rr.template fetch<0>(ru_p, p, tc.z0 + TZ - RC);
+        tr.template fetch<0, false>(T_p, p, tc.z0 + TZ - RC);
+        gr.template fetch<0, false>(gam_p, p, tc.z0, 2 * TZ - 1 - RC);
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            rr.store_all(rst[k], rwin, k);
+            tr.store_all(tst[k], twin, k);
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * TZ - 1; ++j) gr.store_all(gst[j], gwin, (j - RC + 64) % NSG);
     }
     __syncthreads();
     const int lbase = (tc.ly + RC) * LX + (tc.lx + RC), gcen = (tc.ly + O) * LXg + (tc.lx + O);
@@ -473,13 +484,13 @@ __global__ __launch_bounds__(TX *TY) void k_thermal_s0(Geom g, Pad p, const V4<R
         constexpr int c = decltype(ci)::value;
         constexpr int S = (c + RC) & 1;
         if constexpr (c + 1 < RC) {  // for the store at the end of step c + 1
-            rr.template fetch<S ^ 1>(ru_p, p, tc.z0 + c + 2);
-            tr.template fetch<S ^ 1, false>(T_p, p, tc.z0 + c + 2);
-            gr.template fetch<S ^ 1, false>(gam_p, p, tc.z0, c + 2);
+            rr.template fetch<S ^ 1>(ru_p, p, tc.z0 + c + 1 + TZ);
+            tr.template fetch<S ^ 1, false>(T_p, p, tc.z0 + c + 1 + TZ);
+            gr.template fetch<S ^ 1, false>(gam_p, p, tc.z0, c + 2 * TZ);
         }
-        const R *pc = rwin + ((c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
-        const R *tcp = twin + ((c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
-        const R *gc = gwin + ((c + 64) % 2) * gr.LS + gcen - (O + O * LXg);
+        const R *pc = rwin + ((tc.lz + c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
+        const R *tcp = twin + ((tc.lz + c + RC) % NS) * rr.LP + lbase - (RC + RC * LX);
+        const R *gc = gwin + ((c + 2 * tc.lz + 64) % NSG) * gr.LS + gcen - (O + O * LXg);
         __amdgpu_buffer_rsrc_t gnone[4];  // unused: the contact values come from LDS
         static_for<SH::T.qs[c + RC], SH::T.qs[c + RC + 1]>([&](auto qi) __attribute__((always_inline)) {
             constexpr CQuad Q = SH::T.q[decltype(qi)::value];
@@ -549,9 +560,9 @@ __global__ __launch_bounds__(TX *TY) void k_thermal_s0(Geom g, Pad p, const V4<R
         pin(az);
         pin(aT);
         if constexpr (c < RC) {
-            rr.template store<S>(rwin, (c + 1 + RC) % NS);
-            tr.template store<S>(twin, (c + 1 + RC) % NS);
-            gr.template store<S>(gwin, (c + 1 + 64) % 2);
+            rr.template store<S>(rwin, (c + TZ + RC) % NS);
+            tr.template store<S>(twin, (c + TZ + RC) % NS);
+            gr.template store<S>(gwin, (c + 2 * TZ - 1 + 64) % NSG);
         }
         __syncthreads();
     });

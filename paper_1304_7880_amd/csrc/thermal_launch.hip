@@ -26,25 +26,28 @@ wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 }
 
 // compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
-// sigma = 10 their two rings (75 KB) leave room for two blocks per CU; at
-// u = 0 k_thermal_s0 with the contact values in LDS as well (70 KB)
+// sigma = 10 their two rings (75 KB) leave room for two blocks per CU
 template <int S2, bool NoU>
 wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
 {
-    constexpr int TX = 32, TY = 16, TZ = 1, NT = TX * TY * TZ;
+    // at u = 0 k_thermal_s0 on two-plane tiles: its three rings (123 KB at
+    // sigma = 10) for one 1024-lane block per CU, half the barriers and ring
+    // fills per node of one-plane tiles
+    constexpr int TX = 32, TY = 16, TZ = NoU ? 2 : 1, NT = TX * TY * TZ;
     constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
-    static_assert(thermal_lds_bytes(TX, TY, TZ, RC, 4) <= LDS_MAX, "rings fit in LDS");
+    constexpr size_t LDS = NoU ? thermal0_lds_bytes(TX, TY, TZ, RC, 4) : thermal_lds_bytes(TX, TY, TZ, RC, 4);
+    static_assert(LDS <= LDS_MAX, "rings fit in LDS");
     if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
     const Geom g = c->g;
     const double s = c->prm.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
-    // at u = 0: the density, T and contact-value rings of k_thermal_s0
-    static_assert(thermal0_lds_bytes(TX, TY, RC, 4) <= LDS_MAX, "rings fit in LDS");
-    const size_t lds = NoU ? thermal0_lds_bytes(TX, TY, RC, 4) : thermal_lds_bytes(TX, TY, TZ, RC, 4);
-    auto kern = NoU ? k_thermal_s0<float, S2, TX, TY> : k_thermal_s<float, S2, TX, TY, TZ, NR, false>;
-    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    auto kern = [] {
+        if constexpr (NoU) return k_thermal_s0<float, S2, TX, TY, TZ>;
+        else return k_thermal_s<float, S2, TX, TY, TZ, NR, false>;
+    }();
+    HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS));
     return launch(c, K_THERMAL, [&] {
-        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), lds, c->stream, g, c->pad,
+        hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), LDS, c->stream, g, c->pad,
                            (const V4<float> *)c->ru1_p, (const float *)c->rho_p, (const float *)c->gam_p,
                            float(s * s), tx, ty, tz, Q, B, FT);
     });
