@@ -259,9 +259,12 @@ wdlb_status wdlb_conduction_at_rest(wdlb_ctx *ctx, const double *h_n, double *h_
  * 1/6 at the largest T, the kinetic part).  Asynchronous on the context's
  * stream like wdlb_step: a density or temperature that is not positive and
  * finite at a step's start is reported as WDLB_E_UNSTABLE by the next
- * synchronising call (and the state is then not meaningful).  Runs eagerly
- * (no graph replay).  The state can be read, saved and stepped
- * isothermally as any other; the field reads give the isothermal forces. */
+ * synchronising call (and the state is then not meaningful).  Pairs of
+ * steps replay a captured graph as in wdlb_step (not while kernels are
+ * timed, nor once wdlb_set_graphs has turned replay off); a call with
+ * another d_T or nsub captures anew.  The state can be read, saved and
+ * stepped isothermally as any other; the field reads give the isothermal
+ * forces. */
 wdlb_status wdlb_init_thermal(wdlb_ctx *ctx, const double *h_n, const double *h_u, const double *h_T, void *d_T);
 wdlb_status wdlb_step_thermal(wdlb_ctx *ctx, void *d_T, int64_t nsteps, int32_t nsub);
 
@@ -323,11 +326,11 @@ const char *wdlb_kernel_name(int32_t kernel);
 wdlb_status wdlb_set_tile(wdlb_ctx *ctx, int32_t variant);
 wdlb_status wdlb_get_tile(wdlb_ctx *ctx, int32_t *variant, int32_t *specialised);
 
-/* wdlb_step replays pairs of steps as HIP graphs (captured on first use on
- * a private stream, launched on the context's stream) unless kernel timing
- * is on or the mode is WDLB_BF16_NEQ; the result is the same as stepping
- * launch by launch.  wdlb_set_graphs(ctx, 0) turns replay off (1: on, the
- * default). */
+/* wdlb_step and wdlb_step_thermal replay pairs of steps as HIP graphs
+ * (captured on first use on a private stream, launched on the context's
+ * stream) unless kernel timing is on or the mode is WDLB_BF16_NEQ; the
+ * result is the same as stepping launch by launch.  wdlb_set_graphs(ctx, 0)
+ * turns replay off (1: on, the default). */
 wdlb_status wdlb_set_graphs(wdlb_ctx *ctx, int32_t enable);
 
 /* Message of the last failed call on this context ("" if none).  The

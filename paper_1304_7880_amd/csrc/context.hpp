@@ -69,6 +69,10 @@ struct wdlb_ctx {
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int graph_nz_run = -1;
+    // the same for pairs of coupled thermal-flow steps, for one T array and nsub
+    hipGraphExec_t tgexec[2] = {nullptr, nullptr};
+    void *tg_T = nullptr;
+    int tg_nsub = 0;
     int nz_run;        // planes the step kernels process (nz; fewer in a partly filled stacked lattice)
     int64_t step;
     bool inited;

@@ -311,6 +311,12 @@ void drop_graphs(wdlb_ctx *c)
             (void)hipGraphExecDestroy(e);
             e = nullptr;
         }
+    for (auto &e : c->tgexec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    c->tg_T = nullptr;
 }
 
 wdlb_status tables(wdlb_ctx *c)
@@ -1054,6 +1060,57 @@ static wdlb_status step_graph(wdlb_ctx *c, hipGraphExec_t *ex)
     return WDLB_OK;
 }
 
+// a graph of two coupled thermal-flow steps from the current parity, for
+// the T array d_T and nsub sub-steps (captured as step_graph captures the
+// isothermal pair; a new T array or nsub drops the pair)
+static wdlb_status thermal_graph(wdlb_ctx *c, void *d_T, int nsub, hipGraphExec_t *ex)
+{
+    if (c->graph_nz_run != c->nz_run) {
+        drop_graphs(c);
+        c->graph_nz_run = c->nz_run;
+    }
+    if (c->tg_T != d_T || c->tg_nsub != nsub) {
+        for (auto &e : c->tgexec)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+        c->tg_T = d_T;
+        c->tg_nsub = nsub;
+    }
+    const int par = c->cur;
+    if (!c->tgexec[par]) {
+        if (!c->cap && hipStreamCreate(&c->cap) != hipSuccess) {
+            c->graphs = false;
+            return WDLB_OK;
+        }
+        hipStream_t keep = c->stream;
+        c->stream = c->cap;
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+        wdlb_status st = WDLB_OK;
+        if (ok) {
+            st = thermal_flow_step(c, d_T, nsub);
+            c->cur ^= 1;
+            if (st == WDLB_OK) st = thermal_flow_step(c, d_T, nsub);
+            c->cur ^= 1;
+            ok = hipStreamEndCapture(c->cap, &graph) == hipSuccess && st == WDLB_OK && graph != nullptr;
+        }
+        c->stream = keep;
+        hipGraphExec_t e = nullptr;
+        if (ok) ok = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (!ok) {
+            c->graphs = false;  // step eagerly from now on
+            return WDLB_OK;
+        }
+        c->tgexec[par] = e;
+    }
+    *ex = c->tgexec[par];
+    return WDLB_OK;
+}
+
 static wdlb_status do_init(wdlb_ctx *c, int uniform, const double u0[3], const double *h_n, const double *h_u)
 {
     const Geom g = c->g;
@@ -1245,6 +1302,17 @@ wdlb_status wdlb_step_thermal(wdlb_ctx *c, void *d_T, int64_t nsteps, int32_t ns
     wdlb_status st = thermal_flow_ok(c);
     if (st != WDLB_OK) return st;
     if (!c->inited) return fail(c, WDLB_E_STATE, "context not initialised");
+    // pairs of steps by graph replay (not while kernels are timed), as wdlb_step
+    if (c->graphs && c->prof == 0) {
+        while (nsteps >= 2) {
+            hipGraphExec_t ex = nullptr;
+            if ((st = thermal_graph(c, d_T, nsub, &ex)) != WDLB_OK) return st;
+            if (!ex) break;  // capture not available: step eagerly
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+            c->step += 2;
+            nsteps -= 2;
+        }
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
         if ((st = thermal_flow_step(c, d_T, nsub)) != WDLB_OK) return st;
         c->cur ^= 1;

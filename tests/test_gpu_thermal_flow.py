@@ -363,3 +363,25 @@ def test_allocation_free_context_steps_the_same():
         out.append((ctx.read_populations(), ctx.read_temperature()))
         ctx.destroy()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_local64"])
+def test_graph_replay_equals_eager_steps(prec):
+    """Six coupled steps in one call (three graph replays of two steps, the
+    graph captured for this T and nsub) against six eager steps: the same
+    bits; then a call with another nsub (a new capture) and a single step
+    (eager) keep them equal."""
+    nx, ny, nz, sigma, eta, tau = 20, 13, 15, 4.0, 0.3, 0.9
+    n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=91)
+    T0 = random_temperature(nx, ny, nz, KT, 0.05, seed=92)
+    out = []
+    for graphs in (True, False):
+        ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, (1e-4, 0.0, 0.0))
+        ctx.set_graphs(graphs)
+        ctx.init_thermal(n, u, T0)
+        ctx.step_thermal(6, 4)
+        ctx.step_thermal(2, 5)
+        ctx.step_thermal(1, 4)
+        out.append((ctx.read_populations(), ctx.read_temperature()))
+        ctx.destroy()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
