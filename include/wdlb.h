@@ -309,16 +309,19 @@ const char *wdlb_kernel_name(int32_t kernel);
  *   6     32 x 8 x 2 nodes, (rho, u1) staged in LDS, contact values read
  *         through the caches.
  * wdlb_set_tile(ctx, -1) (the default) picks variant 5 for lattices at most
- * 16 nodes wide in x when it fits; else, in FP32 with a compiled shell
- * (sigma = 3, 4, 6, 8 or 10), variant 6; else the first of 0..4 whose LDS
- * rings fit the shell reach of sigma.  For sigma = 3, 4, 6, 8 or 10 it runs
+ * 16 nodes wide in x when it fits, else the first of 0..4 whose LDS rings
+ * fit the shell reach of sigma.  For sigma = 3, 4, 6, 8 or 10 it runs
  * kernels compiled for that shell (offsets and weights fixed at compile
- * time) on variant 6, on variant 5 at sigma = 4 in FP32, and on the chosen
- * one of 0..3 in FP64.  A variant >= 0 forces that tile with the
+ * time): on the chosen one of 0..3, or of 5 at sigma = 4 in FP32; at
+ * sigma = 8 or 10 in FP32 the viscous/SMDB kernel moves to variant 6 (the
+ * variant reported); in FP64 at sigma = 10, where no tile holds both LDS
+ * rings, the viscous/SMDB kernel runs compiled on variant 6 (reported) and
+ * the mean-field kernel table-driven on variant 4.  Variant 6 needs a
+ * padded sub-lattice below 2e9 bytes.  A variant >= 0 forces that tile with the
  * table-driven kernels and fails with WDLB_E_INVAL, leaving the previous
  * choice, when it does not fit.  wdlb_set_params re-applies the request for
  * the new sigma.  wdlb_get_tile returns the variant in use and (if
- * specialised is not NULL) 1 when the compiled-shell kernels run, else 0.
+ * specialised is not NULL) 1 when compiled-shell kernels run, else 0.
  * wdlb_thermal_fields follows the same request: its compiled-shell kernel
  * (FP32, sigma = 3, 4, 6, 8 or 10) runs only under the automatic choice,
  * its table-driven kernels (same result, bit for bit) under a forced one. */

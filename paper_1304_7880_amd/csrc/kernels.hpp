@@ -1273,10 +1273,13 @@ __device__ __forceinline__ R gamma_img(const R *gc, const __amdgpu_buffer_rsrc_t
     constexpr int ox = (SA * A) >> 1, oy = (SB * B) >> 1;
     if constexpr (GL) {
         return gc[(H & 3) * LG + (O + ox) + (O + oy) * LXg];
-    } else {
-        static_assert(sizeof(R) == 4, "contact values through buffer loads are FP32");
+    } else if constexpr (sizeof(R) == 4) {
         return __uint_as_float(
             __builtin_amdgcn_raw_buffer_load_b32(gr[H & 3], (int)gvo, ((oy + O) * PX + (ox + O)) * 4, 0));
+    } else {
+        static_assert(sizeof(R) == 8, "contact values through buffer loads are FP32 or FP64");
+        return __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(gr[H & 3], (int)gvo, ((oy + O) * PX + (ox + O)) * 8, 0));
     }
 }
 

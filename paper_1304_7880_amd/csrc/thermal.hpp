@@ -218,7 +218,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_r(Geom g, Pad p, int Rr,
     th_finish<R>(g, x, y, z, c0.x, T0, s2, ax, ay, az, aT, NoU ? R(0) : aV, Qo, Bo, FTo);
 }
 
-// k_thermal_s: the same sums compiled for the shell of 2 sigma = S2 (FP32):
+// k_thermal_s: the same sums compiled for the shell of 2 sigma = S2:
 // the e_z steps and the groups unrolled, every LDS offset an immediate,
 // every weight a literal; the contact values by buffer loads whose image
 // offset is a scalar (see gamma_img).  Groups with a or b zero sum their
@@ -230,7 +230,6 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_thermal_s(Geom g, Pad p, const V
                                                           R s2, int tiles_x, int tiles_y, int tiles_z,
                                                           R *__restrict__ Qo, R *__restrict__ Bo, R *__restrict__ FTo)
 {
-    static_assert(sizeof(R) == 4, "compiled thermal sums read the contact values by FP32 buffer loads");
     using SH = Shell<S2>;
     constexpr int RC = SH::R, LX = TX + 2 * RC, O = (RC + 1) >> 1, NT = TX * TY * TZ, NS = TZ + 1;
     extern __shared__ __align__(16) unsigned char lds_raw[];

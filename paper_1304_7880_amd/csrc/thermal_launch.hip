@@ -27,48 +27,54 @@ wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 
 // compiled for the shell of 2 sigma = S2 (FP32) on 32 x 16 x 1 tiles: at
 // sigma = 10 their two rings (75 KB) leave room for two blocks per CU
-template <int S2, bool NoU>
-wdlb_status launch_thermal_s(wdlb_ctx *c, float *Q, float *B, float *FT)
+template <typename R, int S2, bool NoU>
+wdlb_status launch_thermal_s(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
-    // at u = 0 k_thermal_s0 on two-plane tiles: its three rings (123 KB at
-    // sigma = 10) for one 1024-lane block per CU, half the barriers and ring
-    // fills per node of one-plane tiles
-    constexpr int TX = 32, TY = 16, TZ = NoU ? 2 : 1, NT = TX * TY * TZ;
+    // FP32 at u = 0: k_thermal_s0 on two-plane tiles, its three rings (123 KB
+    // at sigma = 10) for one 1024-lane block per CU, half the barriers and
+    // ring fills per node of one-plane tiles.  Otherwise k_thermal_s on
+    // one-plane tiles (in FP64 its two rings take 146 KB at sigma = 10).
+    constexpr bool S0 = NoU && std::is_same<R, float>::value;
+    constexpr int TX = 32, TY = 16, TZ = S0 ? 2 : 1, NT = TX * TY * TZ;
     constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
-    constexpr size_t LDS = NoU ? thermal0_lds_bytes(TX, TY, TZ, RC, 4) : thermal_lds_bytes(TX, TY, TZ, RC, 4);
+    constexpr size_t LDS = S0 ? thermal0_lds_bytes(TX, TY, TZ, RC, sizeof(R)) : thermal_lds_bytes(TX, TY, TZ, RC, sizeof(R));
     static_assert(LDS <= LDS_MAX, "rings fit in LDS");
     if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
     const Geom g = c->g;
     const double s = c->prm.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
     auto kern = [] {
-        if constexpr (NoU) return k_thermal_s0<float, S2, TX, TY, TZ>;
-        else return k_thermal_s<float, S2, TX, TY, TZ, NR, false>;
+        if constexpr (S0) return k_thermal_s0<float, S2, TX, TY, TZ>;
+        else return k_thermal_s<R, S2, TX, TY, TZ, NR, NoU>;
     }();
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS));
     return launch(c, K_THERMAL, [&] {
         hipLaunchKernelGGL(kern, dim3((unsigned)(tx * ty * tz)), dim3(NT), LDS, c->stream, g, c->pad,
-                           (const V4<float> *)c->ru1_p, (const float *)c->rho_p, (const float *)c->gam_p,
-                           float(s * s), tx, ty, tz, Q, B, FT);
+                           (const V4<R> *)c->ru1_p, (const R *)c->rho_p, (const R *)c->gam_p, R(s * s), tx, ty,
+                           tz, Q, B, FT);
     });
 }
 
 template <typename R, bool NoU>
 wdlb_status launch_thermal(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
-    if constexpr (std::is_same<R, float>::value) {
-        // the buffer loads of the contact values take a lane offset below
-        // 2^31 bytes into one padded sub-lattice; a forced shell tile
-        // (wdlb_set_tile >= 0) selects the table-driven kernels here too
-        if (c->tile_req < 0 && 4.0 * (double)c->pad.NP < 2.0e9) {
+    // the buffer loads of the contact values take a lane offset below 2^31
+    // bytes into one padded sub-lattice; a forced shell tile (wdlb_set_tile
+    // >= 0) selects the table-driven kernels here too
+    if (c->tile_req < 0 && (double)sizeof(R) * (double)c->pad.NP < 2.0e9) {
+        if constexpr (std::is_same<R, float>::value) {
             switch (specialised_s2(c->prm.sigma)) {
-            case 6: return launch_thermal_s<6, NoU>(c, Q, B, FT);
-            case 8: return launch_thermal_s<8, NoU>(c, Q, B, FT);
-            case 12: return launch_thermal_s<12, NoU>(c, Q, B, FT);
-            case 16: return launch_thermal_s<16, NoU>(c, Q, B, FT);
-            case 20: return launch_thermal_s<20, NoU>(c, Q, B, FT);
+            case 6: return launch_thermal_s<R, 6, NoU>(c, Q, B, FT);
+            case 8: return launch_thermal_s<R, 8, NoU>(c, Q, B, FT);
+            case 12: return launch_thermal_s<R, 12, NoU>(c, Q, B, FT);
+            case 16: return launch_thermal_s<R, 16, NoU>(c, Q, B, FT);
+            case 20: return launch_thermal_s<R, 20, NoU>(c, Q, B, FT);
             default: break;
             }
+        } else {
+            // FP64: the shell of sigma = 10 only, where the table-driven
+            // kernels are slowest
+            if (specialised_s2(c->prm.sigma) == 20) return launch_thermal_s<R, 20, NoU>(c, Q, B, FT);
         }
     }
     constexpr int TZ = std::is_same<R, float>::value ? 2 : 1;

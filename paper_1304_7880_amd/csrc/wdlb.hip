@@ -286,6 +286,16 @@ wdlb_status upload_tables(wdlb_ctx *c)
             c->tile = L1G_TILE;
         if (c->tile >= 0 && compiled_shell<R>(s2c, c->tile_mf, reach) && compiled_shell<R>(s2c, c->tile, reach))
             c->spec_s2 = s2c;
+        // the FP64 shell for which no tile holds both LDS rings (2 sigma = 20,
+        // the largest compiled shell): the viscous/SMDB kernel runs compiled
+        // on the cache-gamma tile, the mean-field kernel table-driven on the
+        // automatic tile (same buffer offset bound as above)
+        if (std::is_same<R, double>::value && c->spec_s2 == 0 && s2c == 20 && c->tile >= 0 &&
+            c->tile != NARROW_TILE && tile_fits(SHELL_TILES[L1G_TILE], reach, sizeof(R)) &&
+            (double)sizeof(R) * (double)c->pad.NP < 2.0e9) {
+            c->tile = L1G_TILE;
+            c->spec_s2 = s2c;
+        }
         if (compiled_density<R>(s2c, dtile, rb)) c->spec_b2 = s2c;
     }
     if (c->tile < 0) return fail(c, WDLB_E_INVAL, "sigma too large for the shell tiles");
@@ -363,6 +373,27 @@ wdlb_status launch_shell_pair(wdlb_ctx *c)
     });
 }
 
+// the viscous/SMDB kernel compiled for the shell 2 sigma = S2 on tile TIS
+template <typename R, int S2, int TIS>
+wdlb_status launch_visc_s(wdlb_ctx *c)
+{
+    constexpr int RC = Shell<S2>::R;
+    constexpr ShellTile T = SHELL_TILES[TIS];
+    const Geom g = c->g;
+    const wdlb_params &p = c->prm;
+    const double s = p.sigma;
+    const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
+    const size_t lsh = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(V4<R>), sizeof(R), T.NG > 0);
+    auto ksh = k_shell_s<R, S2, T.TX, T.TY, T.TZ, T.NR, T.NG>;
+    HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
+    return launch(c, K_SHELL, [&] {
+        hipLaunchKernelGGL(ksh, dim3(tx * ty * tz), dim3(T.TX * T.TY * T.TZ), lsh, c->stream, g, c->pad,
+                           (const V4<R> *)c->ru1_p, (const R *)c->gam_p, (const V4<R> *)c->fmf,
+                           R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]),
+                           R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A, (R *)c->shell_trace);
+    });
+}
+
 // the pair specialised for the shell 2 sigma = S2: the mean-field kernel on
 // tile TIM, the viscous/SMDB kernel on tile TIS
 template <typename R, int S2, int TIM, int TIS>
@@ -394,18 +425,42 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
             });
         }
         if (st != WDLB_OK || !(c->shell_part & 2)) return st;
-        constexpr ShellTile T = SHELL_TILES[TIS];
-        const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
-        const size_t lsh = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(V4<R>), sizeof(R), T.NG > 0);
-        auto ksh = k_shell_s<R, S2, T.TX, T.TY, T.TZ, T.NR, T.NG>;
-        HIPCHK(c, hipFuncSetAttribute((const void *)ksh, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
-        return launch(c, K_SHELL, [&] {
-            hipLaunchKernelGGL(ksh, dim3(tx * ty * tz), dim3(T.TX * T.TY * T.TZ), lsh, c->stream, g, c->pad,
-                               (const V4<R> *)c->ru1_p, (const R *)c->gam_p, (const V4<R> *)c->fmf,
-                               R(2.0 * s * s * std::sqrt(KT / M_PI)), R(-(KT / 5.0) * s * s), R(p.g[0]), R(p.g[1]),
-                               R(p.g[2]), p.smdb, tx, ty, tz, (R *)c->F, (R *)c->A, (R *)c->shell_trace);
-        });
+        return launch_visc_s<R, S2, TIS>(c);
     }
+}
+
+// the table-driven pair on one tile
+template <typename R>
+wdlb_status launch_shell_table(wdlb_ctx *c, int tile)
+{
+    static_assert(NTILES == 7, "one case per entry of SHELL_TILES");
+    switch (tile) {
+    case 0: return launch_shell_pair<R, 32, 8, 2, 2, 5>(c);
+    case 1: return launch_shell_pair<R, 32, 8, 2, 3, 6>(c);
+    case 2: return launch_shell_pair<R, 32, 8, 2, 4, 8>(c);
+    case 3: return launch_shell_pair<R, 32, 16, 1, 7, 13>(c);
+    case 4: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
+    case 5: return launch_shell_pair<R, 16, 16, 2, 2, 5>(c);
+    default: return launch_shell_pair<R, 32, 8, 2, 4, 0>(c);
+    }
+}
+
+// the table-driven mean-field kernel on tile_mf, then the viscous/SMDB
+// kernel compiled for the shell 2 sigma = S2 on the cache-gamma tile
+template <typename R, int S2>
+wdlb_status launch_shell_mixed_s(wdlb_ctx *c)
+{
+    if (c->tile != L1G_TILE || c->tile_mf == L1G_TILE || c->reach != Shell<S2>::R)
+        return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
+    const int part = c->shell_part;
+    wdlb_status st = WDLB_OK;
+    if (part & 1) {
+        c->shell_part = 1;
+        st = launch_shell_table<R>(c, c->tile_mf);
+        c->shell_part = part;
+    }
+    if (st != WDLB_OK || !(part & 2)) return st;
+    return launch_visc_s<R, S2, L1G_TILE>(c);
 }
 
 template <typename R>
@@ -414,6 +469,9 @@ wdlb_status launch_shells(wdlb_ctx *c)
 #define WDLB_TW(S2) pick_tile_wide(Shell<S2>::R, sizeof(R))
 #define WDLB_WIDE(S2) launch_shell_pair_s<R, S2, WDLB_TW(S2), WDLB_TW(S2)>(c)
     if (c->spec_s2 > 0) {
+        if constexpr (std::is_same<R, double>::value) {
+            if (c->tile == L1G_TILE && c->spec_s2 == 20) return launch_shell_mixed_s<R, 20>(c);
+        }
         if constexpr (std::is_same<R, float>::value) {
             if (c->tile == NARROW_TILE && c->spec_s2 == 8)
                 return launch_shell_pair_s<R, 8, NARROW_TILE, NARROW_TILE>(c);
@@ -437,16 +495,7 @@ wdlb_status launch_shells(wdlb_ctx *c)
     }
 #undef WDLB_WIDE
 #undef WDLB_TW
-    static_assert(NTILES == 7, "one case per entry of SHELL_TILES");
-    switch (c->tile) {
-    case 0: return launch_shell_pair<R, 32, 8, 2, 2, 5>(c);
-    case 1: return launch_shell_pair<R, 32, 8, 2, 3, 6>(c);
-    case 2: return launch_shell_pair<R, 32, 8, 2, 4, 8>(c);
-    case 3: return launch_shell_pair<R, 32, 16, 1, 7, 13>(c);
-    case 4: return launch_shell_pair<R, 16, 16, 1, 10, 0>(c);
-    case 5: return launch_shell_pair<R, 16, 16, 2, 2, 5>(c);
-    default: return launch_shell_pair<R, 32, 8, 2, 4, 0>(c);
-    }
+    return launch_shell_table<R>(c, c->tile);
 }
 
 template <typename R, int TX, int TY, int TZ>

@@ -151,8 +151,11 @@ def test_compiled_shell_equals_table_driven(sigma, prec):
             ctx.set_tile(tile)
             assert ctx.get_tile() == (tile, False)
         else:
-            # FP64 at sigma = 10 only fits the tile that reads gamma through the caches
-            assert spec == (prec == "fp32" or sigma < 10), (tile, spec)
+            # FP64 at sigma = 10: the compiled viscous kernel on the tile that
+            # reads gamma through the caches, the mean-field one table-driven
+            assert spec, (tile, spec)
+            if sigma == 10.0 or (sigma == 8.0 and prec == "fp32"):
+                assert tile == 6, tile
         ctx.init_fields(n, u)
         ctx.step(3)
         out.append(ctx.read_fields(with_forces=True))

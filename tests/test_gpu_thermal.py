@@ -188,16 +188,18 @@ def test_full_size_slab_z_profile_against_column():
     assert max(eq, eb, ef) < 2e-5
 
 
-@pytest.mark.parametrize("sigma,shape", [(6.0, (40, 24, 30)), (10.0, (70, 20, 26))])
-def test_compiled_and_table_driven_kernels_agree_bitwise(sigma, shape):
-    """FP32 at a compiled shell: the compiled kernel (automatic choice) and
-    the table-driven ring kernel (a forced shell tile) give the same bits."""
+@pytest.mark.parametrize("prec,sigma,shape", [("fp32", 6.0, (40, 24, 30)), ("fp32", 10.0, (70, 20, 26)),
+                                              ("fp64", 10.0, (70, 20, 26))])
+def test_compiled_and_table_driven_kernels_agree_bitwise(prec, sigma, shape):
+    """At a compiled shell (FP32; FP64 at sigma = 10): the compiled kernel
+    (automatic choice) and the table-driven ring kernel (a forced shell tile)
+    give the same bits."""
     nx, ny, nz = shape
     n, u = random_fields(nx, ny, nz, packing_to_density(0.3, sigma), 0.05, 0.01, seed=4)
     T = random_temperature(nx, ny, nz, 1.0 / 3.0, 0.1, seed=5)
     outs = []
     for forced in (False, True):
-        ctx = _ctx(nx, ny, nz, True, "fp32", sigma)
+        ctx = _ctx(nx, ny, nz, True, prec, sigma)
         if forced:
             ctx.set_tile(6)
         outs.append(ctx.thermal_fields(n, u, T))

@@ -321,18 +321,19 @@ def test_checkpoint_and_resume():
     assert np.array_equal(fa, fb) and np.array_equal(Ta, Tb)
 
 
-@pytest.mark.parametrize("sigma", [6.0, 10.0])
-def test_compiled_and_table_driven_kernels_give_the_same_bits(sigma):
+@pytest.mark.parametrize("prec,sigma", [("fp32_local64", 6.0), ("fp32_local64", 10.0), ("fp64", 10.0)])
+def test_compiled_and_table_driven_kernels_give_the_same_bits(prec, sigma):
     """The coupled step on the kernels compiled for the shell (the shells, the
-    thermal sums at u = 0 with their density ring) and on the table-driven
+    thermal sums at u = 0 with their density ring in FP32; in FP64 at
+    sigma = 10 the viscous kernel with its trace sums) and on the table-driven
     kernels of the same tiles: the same populations and T, bit for bit, after
-    three steps on a walled lattice with ragged tiles (FP32 storage)."""
+    three steps on a walled lattice with ragged tiles."""
     nx, ny, nz, eta, tau = 37, 19, 2 * int(sigma) + 9, 0.3, 0.85
     n, u = random_fields(nx, ny, nz, packing_to_density(eta, sigma), 0.05, 0.01, seed=71)
     T0 = random_temperature(nx, ny, nz, KT, 0.05, seed=72)
     out = []
     for forced in (False, True):
-        ctx = _ctx(nx, ny, nz, True, "fp32_local64", sigma, eta, tau, (1e-4, 2e-5, 0.0))
+        ctx = _ctx(nx, ny, nz, True, prec, sigma, eta, tau, (1e-4, 2e-5, 0.0))
         tile, spec = ctx.get_tile()
         if forced:
             ctx.set_tile(tile)
