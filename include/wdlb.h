@@ -315,9 +315,9 @@ const char *wdlb_kernel_name(int32_t kernel);
  * time): on the chosen one of 0..3, or of 5 at sigma = 4 in FP32; at
  * sigma = 8 or 10 in FP32 the viscous/SMDB kernel moves to variant 6 (the
  * variant reported); in FP64 at sigma = 10, where no tile holds both LDS
- * rings, the viscous/SMDB kernel runs compiled on variant 6 (reported) and
- * the mean-field kernel table-driven on variant 4.  Variant 6 needs a
- * padded sub-lattice below 2e9 bytes.  A variant >= 0 forces that tile with the
+ * rings of the viscous/SMDB kernel, it runs compiled on variant 6 (the
+ * variant reported) and the mean-field kernel compiled on variant 1.
+ * Variant 6 needs a padded sub-lattice below 2e9 bytes.  A variant >= 0 forces that tile with the
  * table-driven kernels and fails with WDLB_E_INVAL, leaving the previous
  * choice, when it does not fit.  wdlb_set_params re-applies the request for
  * the new sigma.  wdlb_get_tile returns the variant in use and (if

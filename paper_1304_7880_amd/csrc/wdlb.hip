@@ -209,6 +209,21 @@ constexpr int pick_tile_wide(int reach, size_t rbytes)
     return -1;
 }
 
+// the first of the variants 0..3 whose rings hold those of the mean-field
+// kernel alone (its plane ring holds rho, not (rho, u1)), or -1
+constexpr int pick_tile_mf(int reach, size_t rbytes)
+{
+    for (int k = 0; k < 4; ++k) {
+        const ShellTile &t = SHELL_TILES[k];
+        const int NT = t.TX * t.TY * t.TZ;
+        const int LP = (t.TX + 2 * reach) * (t.TY + 2 * reach), LS = 4 * (t.TX + reach) * (t.TY + reach);
+        if ((LP + NT - 1) / NT <= t.NR && (LS + NT - 1) / NT <= t.NG &&
+            shell_lds_bytes(t.TX, t.TY, t.TZ, reach, rbytes, rbytes, true) <= LDS_MAX)
+            return k;
+    }
+    return -1;
+}
+
 constexpr int pick_tile(int reach, size_t rbytes, int nx)
 {
     if (nx <= 16 && tile_fits(SHELL_TILES[NARROW_TILE], reach, rbytes)) return NARROW_TILE;
@@ -286,14 +301,16 @@ wdlb_status upload_tables(wdlb_ctx *c)
             c->tile = L1G_TILE;
         if (c->tile >= 0 && compiled_shell<R>(s2c, c->tile_mf, reach) && compiled_shell<R>(s2c, c->tile, reach))
             c->spec_s2 = s2c;
-        // the FP64 shell for which no tile holds both LDS rings (2 sigma = 20,
-        // the largest compiled shell): the viscous/SMDB kernel runs compiled
-        // on the cache-gamma tile, the mean-field kernel table-driven on the
-        // automatic tile (same buffer offset bound as above)
+        // the FP64 shell for which no tile holds both LDS rings of the
+        // viscous/SMDB kernel (2 sigma = 20, the largest compiled shell): it
+        // runs compiled on the cache-gamma tile, the compiled mean-field
+        // kernel on the first tile that holds its own two rings (same buffer
+        // offset bound as above)
         if (std::is_same<R, double>::value && c->spec_s2 == 0 && s2c == 20 && c->tile >= 0 &&
             c->tile != NARROW_TILE && tile_fits(SHELL_TILES[L1G_TILE], reach, sizeof(R)) &&
-            (double)sizeof(R) * (double)c->pad.NP < 2.0e9) {
+            pick_tile_mf(reach, sizeof(R)) >= 0 && (double)sizeof(R) * (double)c->pad.NP < 2.0e9) {
             c->tile = L1G_TILE;
+            c->tile_mf = pick_tile_mf(reach, sizeof(R));
             c->spec_s2 = s2c;
         }
         if (compiled_density<R>(s2c, dtile, rb)) c->spec_b2 = s2c;
@@ -414,7 +431,7 @@ wdlb_status launch_shell_pair_s(wdlb_ctx *c)
         if (c->shell_part & 1) {
             constexpr ShellTile T = SHELL_TILES[TIM];
             const int tx = (g.nx + T.TX - 1) / T.TX, ty = (g.ny + T.TY - 1) / T.TY, tz = (c->nz_run + T.TZ - 1) / T.TZ;
-            const size_t lmf = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(R), sizeof(R), true);
+            const size_t lmf = shell_lds_bytes(T.TX, T.TY, T.TZ, RC, sizeof(R), sizeof(R), T.NG > 0);
             auto kmf = k_meanfield_s<R, S2, T.TX, T.TY, T.TZ, T.NR, T.NG>;
             HIPCHK(c, hipFuncSetAttribute((const void *)kmf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmf));
             st = launch(c, K_MEANFIELD, [&] {
@@ -445,24 +462,6 @@ wdlb_status launch_shell_table(wdlb_ctx *c, int tile)
     }
 }
 
-// the table-driven mean-field kernel on tile_mf, then the viscous/SMDB
-// kernel compiled for the shell 2 sigma = S2 on the cache-gamma tile
-template <typename R, int S2>
-wdlb_status launch_shell_mixed_s(wdlb_ctx *c)
-{
-    if (c->tile != L1G_TILE || c->tile_mf == L1G_TILE || c->reach != Shell<S2>::R)
-        return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
-    const int part = c->shell_part;
-    wdlb_status st = WDLB_OK;
-    if (part & 1) {
-        c->shell_part = 1;
-        st = launch_shell_table<R>(c, c->tile_mf);
-        c->shell_part = part;
-    }
-    if (st != WDLB_OK || !(part & 2)) return st;
-    return launch_visc_s<R, S2, L1G_TILE>(c);
-}
-
 template <typename R>
 wdlb_status launch_shells(wdlb_ctx *c)
 {
@@ -470,7 +469,8 @@ wdlb_status launch_shells(wdlb_ctx *c)
 #define WDLB_WIDE(S2) launch_shell_pair_s<R, S2, WDLB_TW(S2), WDLB_TW(S2)>(c)
     if (c->spec_s2 > 0) {
         if constexpr (std::is_same<R, double>::value) {
-            if (c->tile == L1G_TILE && c->spec_s2 == 20) return launch_shell_mixed_s<R, 20>(c);
+            if (c->tile == L1G_TILE && c->spec_s2 == 20)
+                return launch_shell_pair_s<R, 20, pick_tile_mf(Shell<20>::R, sizeof(R)), L1G_TILE>(c);
         }
         if constexpr (std::is_same<R, float>::value) {
             if (c->tile == NARROW_TILE && c->spec_s2 == 8)

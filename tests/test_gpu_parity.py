@@ -151,8 +151,8 @@ def test_compiled_shell_equals_table_driven(sigma, prec):
             ctx.set_tile(tile)
             assert ctx.get_tile() == (tile, False)
         else:
-            # FP64 at sigma = 10: the compiled viscous kernel on the tile that
-            # reads gamma through the caches, the mean-field one table-driven
+            # FP32 at sigma >= 8 and FP64 at sigma = 10: the compiled viscous
+            # kernel on the tile that reads gamma through the caches
             assert spec, (tile, spec)
             if sigma == 10.0 or (sigma == 8.0 and prec == "fp32"):
                 assert tile == 6, tile

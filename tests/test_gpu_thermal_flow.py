@@ -324,8 +324,7 @@ def test_checkpoint_and_resume():
 @pytest.mark.parametrize("prec,sigma", [("fp32_local64", 6.0), ("fp32_local64", 10.0), ("fp64", 10.0)])
 def test_compiled_and_table_driven_kernels_give_the_same_bits(prec, sigma):
     """The coupled step on the kernels compiled for the shell (the shells, the
-    thermal sums at u = 0 with their density ring in FP32; in FP64 at
-    sigma = 10 the viscous kernel with its trace sums) and on the table-driven
+    thermal sums at u = 0, with their density ring in FP32) and on the table-driven
     kernels of the same tiles: the same populations and T, bit for bit, after
     three steps on a walled lattice with ragged tiles."""
     nx, ny, nz, eta, tau = 37, 19, 2 * int(sigma) + 9, 0.3, 0.85
