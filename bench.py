@@ -632,7 +632,7 @@ def main():
     }
     if not args.no_extra:
         modes = {}
-        for prec in ("fp32", "bf16") if args.workload == "slab512" else ():
+        for prec in ("fp32", "bf16", "fp64") if args.workload == "slab512" else ():
             print(f"bench: {w.name}, {prec}", file=sys.stderr, flush=True)
             m = timed_run(w, prec, args.steps, args.warmup, stream)
             modes[prec] = {"mlups": round(m["mlups"], 2), "ms_per_step": round(m["ms_per_step"], 5),
