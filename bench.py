@@ -397,11 +397,11 @@ def thermal_bench(w, prec, reps=5):
 
 def thermal_kernel_name(spec, prec, sigma, at_rest):
     """The thermal-sums kernel the library runs: compiled for the shell
-    (FP32 at a compiled sigma, FP64 at sigma = 10), its u = 0 variant with
-    the density ring in FP32, else the table-driven ring kernel."""
+    (FP32 at a compiled sigma, FP64 at sigma = 10), at u = 0 its variant with
+    all three rings in LDS, else the table-driven ring kernel."""
     if not (spec and (prec != "fp64" or sigma == 10.0)):
         return "k_thermal_r"
-    return "k_thermal_s0" if (at_rest and prec != "fp64") else "k_thermal_s"
+    return "k_thermal_s0" if at_rest else "k_thermal_s"
 
 
 def thermal_flow_bench(w, prec, steps=3, warmup=1, nsub=4):

@@ -422,7 +422,7 @@ struct Thermal0Tile {
     static constexpr int NG = (4 * (TX + RC) * (TY + RC) + NT - 1) / NT;
 };
 
-// The thermal sums at u = 0 compiled for the shell of 2 sigma = S2 (FP32) on
+// The thermal sums at u = 0 compiled for the shell of 2 sigma = S2 on
 // TX x TY x TZ tiles: F^T, B and the conduction part of Q, the velocity not
 // read.  The density, T and the contact values all come from LDS rings
 // that advance along e_z (the contact values as in the mean-field kernel,

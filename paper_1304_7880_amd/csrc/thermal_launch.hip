@@ -30,13 +30,17 @@ wdlb_status launch_thermal_r(wdlb_ctx *c, R *Q, R *B, R *FT)
 template <typename R, int S2, bool NoU>
 wdlb_status launch_thermal_s(wdlb_ctx *c, R *Q, R *B, R *FT)
 {
-    // FP32 at u = 0: k_thermal_s0 on two-plane tiles, its three rings (123 KB
-    // at sigma = 10) for one 1024-lane block per CU, half the barriers and
-    // ring fills per node of one-plane tiles.  Otherwise k_thermal_s on
-    // one-plane tiles (in FP64 its two rings take 146 KB at sigma = 10).
-    constexpr bool S0 = NoU && std::is_same<R, float>::value;
-    constexpr int TX = 32, TY = 16, TZ = S0 ? 2 : 1, NT = TX * TY * TZ;
-    constexpr int RC = Shell<S2>::R, NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
+    // At u = 0 k_thermal_s0 (density, T and contact values in LDS rings): in
+    // FP32 on two-plane tiles, its three rings (123 KB at sigma = 10) for one
+    // 1024-lane block per CU, half the barriers and ring fills per node of
+    // one-plane tiles; in FP64 on one-plane tiles (127 KB at sigma = 10).
+    // Otherwise k_thermal_s on one-plane tiles, the contact values through
+    // the caches (in FP64 its two rings take 146 KB at sigma = 10).
+    constexpr bool F32 = std::is_same<R, float>::value;
+    constexpr int RC = Shell<S2>::R;
+    constexpr bool S0 = NoU && thermal0_lds_bytes(32, 16, F32 ? 2 : 1, RC, sizeof(R)) <= LDS_MAX;
+    constexpr int TX = 32, TY = 16, TZ = S0 && F32 ? 2 : 1, NT = TX * TY * TZ;
+    constexpr int NR = ((TX + 2 * RC) * (TY + 2 * RC) + NT - 1) / NT;
     constexpr size_t LDS = S0 ? thermal0_lds_bytes(TX, TY, TZ, RC, sizeof(R)) : thermal_lds_bytes(TX, TY, TZ, RC, sizeof(R));
     static_assert(LDS <= LDS_MAX, "rings fit in LDS");
     if (c->reach != RC) return fail(c, WDLB_E_STATE, "compiled shell does not match the shell of sigma");
@@ -44,7 +48,7 @@ wdlb_status launch_thermal_s(wdlb_ctx *c, R *Q, R *B, R *FT)
     const double s = c->prm.sigma;
     const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, tz = (g.nz + TZ - 1) / TZ;
     auto kern = [] {
-        if constexpr (S0) return k_thermal_s0<float, S2, TX, TY, TZ>;
+        if constexpr (S0) return k_thermal_s0<R, S2, TX, TY, TZ>;
         else return k_thermal_s<R, S2, TX, TY, TZ, NR, NoU>;
     }();
     HIPCHK(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS));
