@@ -174,13 +174,15 @@ constexpr int L1G_MIN_S2 = 16;
 constexpr int NTILES = (int)(sizeof(SHELL_TILES) / sizeof(SHELL_TILES[0]));
 static_assert(NTILES == WDLB_NTILES, "the header's variant count");
 
-// k_density tiles: 32 x 8 x 2 while its LDS stays within 64 KB (several
-// blocks per CU), else 16 x 8 x 1; lattices at most 16 wide take 16 x 16 x 2
+// k_density tiles: 32 x 8 x 2 while its LDS stays within 96 KB (one block
+// per CU at the FP64 ball of sigma = 10, still faster than the smaller tile
+// and its larger halo per node), else 16 x 8 x 1; lattices at most 16 wide
+// take 16 x 16 x 2
 struct DensityTile {
     int TX, TY, TZ;
     size_t lds_cap;
 };
-constexpr DensityTile DENSITY_TILES[3] = {{32, 8, 2, 64 * 1024}, {16, 8, 1, 160 * 1024}, {16, 16, 2, 64 * 1024}};
+constexpr DensityTile DENSITY_TILES[3] = {{32, 8, 2, 96 * 1024}, {16, 8, 1, 160 * 1024}, {16, 16, 2, 64 * 1024}};
 constexpr int NARROW_DENSITY_TILE = 2;
 constexpr bool density_fits(const DensityTile &t, int rb, size_t rbytes)
 {

@@ -43,7 +43,7 @@ CASES = [
     ("periodic 9x7x11 sigma=4 (stencil wraps)", (9, 7, 11), False, 4.0, 0.25, 1.1, (0.0, 3e-5, 1e-5), 3),
     ("walled 4x4x16 sigma=4 (domain smaller than stencil)", (4, 4, 16), True, 4.0, 0.2, 1.0, (1e-4, 0, 0), 5),
     ("walled 17x5x23 sigma=6", (17, 5, 23), True, 6.0, 0.35, 0.8, (2e-5, 0, 0), 3),
-    # fp64 at sigma = 8: the density kernel runs on its 16x8x1 tiles
+    # 12 wide: the density kernel on the narrow 16x16x2 tiles (table-driven at sigma = 8)
     ("walled 12x9x21 sigma=8", (12, 9, 21), True, 8.0, 0.3, 0.9, (1e-4, 0, 0), 2),
     # 16 wide in x: the narrow 16x16x2 tiles (compiled for sigma = 4 in fp32)
     ("walled 16x16x14 sigma=4 (narrow tiles)", (16, 16, 14), True, 4.0, 0.3, 1.0, (2e-5, 0, 0), 3),
